@@ -1,0 +1,232 @@
+"""Damage sub-problem as a bound-constrained quadratic programme (Sec. 2.2, Sec. 2.4).
+
+Oracle: test infrastructure only.
+
+For element-constant history H_e on P1 triangles the weak forms of
+eq. damage_pde_at2 and eq. damage_pde_at1 give a symmetric system
+A d = b with
+
+  AT2: A = G_c l0 K + sum_e (G_c/l0 + 2 H_e) M^e,   b_i = sum_{e ni i} 2 H_e A_e / 3
+  AT1: A = 3/4 G_c l0 K + sum_e 2 H_e M^e,           b_i = sum_{e ni i} (2 H_e - 3 G_c/(8 l0)) A_e / 3
+
+with K^e_kl = A_e grad phi_k . grad phi_l and the consistent element mass
+M^e_kl = A_e (1 + delta_kl) / 12 of Sec. 2.4.  Irreversibility and the lower
+bound make the update the minimiser of 1/2 d'Ad - b'd over d >= lb with
+lb = d_n (Sec. 2.4, bound enforcement); the upper bound d <= 1 is applied
+afterwards by min(d, 1).  The paper's AT2 alternative (unconstrained solve,
+then clamp to [d_n, 1]) is the 'postclamp' mode.
+
+The exact minimiser is found by a primal-dual active-set iteration with a
+sparse LU solve on the free set; the result is verified against the KKT
+conditions.  Reading: the damage operator uses g = (1-d)^2 without eta.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+import torch
+
+from .fem import Mesh
+
+
+def _pairs(mesh: Mesh):
+    tri = mesh.tri.numpy()
+    rows = np.repeat(tri, 3, axis=1).ravel()        # k repeated over l
+    cols = np.tile(tri, (1, 3)).ravel()
+    return rows, cols
+
+
+def stiffness_matrix(mesh: Mesh) -> sp.csr_matrix:
+    """K = sum_e A_e grad phi_k . grad phi_l (unit diffusion)."""
+    G = mesh.grad.numpy()
+    A = mesh.area.numpy()
+    ke = A[:, None, None] * np.einsum("ekc,elc->ekl", G, G)
+    rows, cols = _pairs(mesh)
+    n = mesh.n_nodes
+    return sp.coo_matrix((ke.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+
+
+def mass_matrix(mesh: Mesh, coef: np.ndarray | None = None) -> sp.csr_matrix:
+    """sum_e coef_e M^e with M^e_kl = A_e (1 + delta_kl)/12."""
+    A = mesh.area.numpy() if coef is None else mesh.area.numpy() * np.asarray(coef)
+    pat = (np.ones((3, 3)) + np.eye(3)) / 12.0
+    me = A[:, None, None] * pat[None]
+    rows, cols = _pairs(mesh)
+    n = mesh.n_nodes
+    return sp.coo_matrix((me.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+
+
+def node_area(mesh: Mesh) -> np.ndarray:
+    """sum_{e ni i} A_e/3 (the integral of the hat function phi_i)."""
+    w = np.zeros(mesh.n_nodes)
+    np.add.at(w, mesh.tri.numpy().ravel(), np.repeat(mesh.area.numpy() / 3.0, 3))
+    return w
+
+
+def damage_coefficients(model: int, Gc: float, l0: float):
+    """(kappa, reaction constant, load constant) of the AT2/AT1 weak form.
+
+    AT2: kappa = Gc l0, c_e = Gc/l0 + 2H_e, load 2H_e.
+    AT1: kappa = 3/4 Gc l0, c_e = 2H_e, load 2H_e - 3Gc/(8 l0).
+    """
+    if model == 2:
+        return Gc * l0, Gc / l0, 0.0
+    if model == 1:
+        return 0.75 * Gc * l0, 0.0, -3.0 * Gc / (8.0 * l0)
+    raise ValueError(model)
+
+
+def assemble_damage(mesh: Mesh, H: np.ndarray, Gc: float, l0: float, model: int, K=None):
+    """Return (A, b) for the current history H (element array)."""
+    H = np.asarray(H, dtype=np.float64)
+    kappa, c0, b0 = damage_coefficients(model, Gc, l0)
+    if K is None:
+        K = stiffness_matrix(mesh)
+    A = (kappa * K + mass_matrix(mesh, c0 + 2.0 * H)).tocsr()
+    b = np.zeros(mesh.n_nodes)
+    np.add.at(b, mesh.tri.numpy().ravel(), np.repeat((2.0 * H + b0) * mesh.area.numpy() / 3.0, 3))
+    return A, b
+
+
+def kkt_residuals(A, b, lb, x):
+    """Scaled KKT violations of min 1/2 x'Ax - b'x, x >= lb.
+
+    Returns (bound violation, max |r_i|/A_ii over free nodes, max r_i/A_ii over
+    nodes at the bound) with r = b - A x.  All three are <= 0 or small at the
+    minimiser.
+    """
+    r = b - A @ x
+    dg = A.diagonal()
+    at = x <= lb
+    free = ~at
+    viol = float(np.max(lb - x)) if len(x) else 0.0
+    rf = float(np.max(np.abs(r[free]) / dg[free])) if free.any() else 0.0
+    ra = float(np.max(r[at] / dg[at])) if at.any() else -np.inf
+    return viol, rf, ra
+
+
+def solve_bound_qp(A, b, lb, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9):
+    """Exact minimiser of 1/2 x'Ax - b'x subject to x >= lb.
+
+    Primal-dual active set: with the multiplier mu = A x - b, a node is
+    active when mu_i - A_ii (x_i - lb_i) > 0; free nodes solve
+    A_FF x_F = b_F - A_FA lb_A exactly.  Stops when the active set repeats.
+    Returns (x, active mask).
+    """
+    A = sp.csr_matrix(A)
+    n = len(b)
+    lb = np.asarray(lb, dtype=np.float64)
+    dg = A.diagonal()
+    x = np.maximum(lb if x0 is None else np.asarray(x0, dtype=np.float64), lb)
+    mu = A @ x - b
+    act = (mu - dg * (x - lb)) > 0
+    seen = set()
+    for _ in range(max_iter):
+        key = act.tobytes()
+        if key in seen:
+            raise RuntimeError("active-set iteration cycled")
+        seen.add(key)
+        free = ~act
+        x = lb.copy()
+        if free.any():
+            Aff = A[free][:, free].tocsc()
+            rhs = b[free] - A[free][:, act] @ lb[act]
+            x[free] = spla.spsolve(Aff, rhs) if free.sum() > 1 else rhs / Aff.toarray()[0, 0]
+        mu = A @ x - b
+        mu[free] = 0.0
+        new_act = (mu - dg * (x - lb)) > 0
+        if np.array_equal(new_act, act):
+            break
+        act = new_act
+    else:
+        raise RuntimeError("active-set iteration did not converge")
+    if check:
+        viol, rf, ra = kkt_residuals(A, b, lb, x)
+        if viol > 0 or rf > tol or ra > tol:
+            raise RuntimeError(f"KKT check failed: viol={viol} rf={rf} ra={ra}")
+    return x, act
+
+
+@dataclass
+class DamageQP:
+    """Damage update of one staggered step for a fixed mesh and model."""
+    mesh: Mesh
+    l0: float
+    model: int
+    bounds: str = "projected"
+
+    def __post_init__(self):
+        self.K = stiffness_matrix(self.mesh)
+        self.M = mass_matrix(self.mesh)
+        self.w = node_area(self.mesh)
+
+    def system(self, H, Gc):
+        return assemble_damage(self.mesh, H, Gc, self.l0, self.model, K=self.K)
+
+    def solve(self, H, Gc, d_prev):
+        """Return (d_new, active, upper, x, A).
+
+        x is the QP minimiser before min(., 1) (projected mode) or the
+        unconstrained solution (post-clamp mode); active marks nodes held at
+        d_prev, upper marks nodes cut by min(., 1).
+        """
+        A, b = self.system(H, Gc)
+        if self.bounds == "projected":
+            x, act = solve_bound_qp(A, b, d_prev, x0=d_prev)
+            upper = x > 1.0
+            return np.minimum(x, 1.0), act, upper, x, A
+        if self.bounds == "postclamp":
+            x = spla.spsolve(A.tocsc(), b)
+            act = x < d_prev
+            xc = np.where(act, d_prev, x)
+            upper = xc > 1.0
+            return np.minimum(xc, 1.0), act, upper, x, A
+        raise ValueError(self.bounds)
+
+    def tangent(self, A, x, act, upper, H, Gc, dH, dGc, dlb):
+        """Directional derivative of the update (implicit rule, Sec. 4.2).
+
+        Free nodes F solve A_FF xdot_F = (bdot - Adot x - A_FA lbdot_A)_F with
+        the active nodes following their bound; nodes cut by min(., 1) get 0.
+        In post-clamp mode the linear solve is unconstrained: A xdot = bdot - Adot x.
+        """
+        kappa_dg = {2: self.l0, 1: 0.75 * self.l0}[self.model]
+        b0_dg = {2: 0.0, 1: -3.0 / (8.0 * self.l0)}[self.model]
+        c0_dg = {2: 1.0 / self.l0, 1: 0.0}[self.model]
+        Adot_x = dGc * (kappa_dg * (self.K @ x) + c0_dg * (self.M @ x)) + mass_matrix(self.mesh, 2.0 * dH) @ x
+        bdot = np.zeros(self.mesh.n_nodes)
+        np.add.at(bdot, self.mesh.tri.numpy().ravel(),
+                  np.repeat((2.0 * dH + dGc * b0_dg) * self.mesh.area.numpy() / 3.0, 3))
+        free = ~act
+        xdot = np.where(act, dlb, 0.0)
+        if self.bounds == "projected":
+            if free.any():
+                rhs = (bdot - Adot_x - A @ xdot)[free]
+                xdot[free] = spla.spsolve(A[free][:, free].tocsc(), rhs)
+        else:
+            full = spla.spsolve(A.tocsc(), bdot - Adot_x)
+            xdot = np.where(act, dlb, full)
+        return np.where(upper, 0.0, xdot)
+
+
+def energies(mesh: Mesh, mass: np.ndarray, v, psi_total, d, Gc: float, l0: float, model: int, K=None, M=None):
+    """Kinetic, elastic and fracture energy per unit thickness.
+
+    E_kin = 1/2 sum m_i |v_i|^2, E_el = sum_e A_e psi_e,
+    E_frac(AT2) = Gc (d'Md/(2 l0) + l0/2 d'Kd),
+    E_frac(AT1) = 3Gc/8 (int d / l0 + l0 d'Kd).
+    """
+    v = np.asarray(v)
+    d = np.asarray(d)
+    K = stiffness_matrix(mesh) if K is None else K
+    e_kin = 0.5 * float(np.sum(np.asarray(mass)[:, None] * v * v))
+    e_el = float(np.sum(mesh.area.numpy() * np.asarray(psi_total)))
+    if model == 2:
+        M = mass_matrix(mesh) if M is None else M
+        e_fr = Gc * (float(d @ (M @ d)) / (2.0 * l0) + 0.5 * l0 * float(d @ (K @ d)))
+    else:
+        e_fr = 3.0 * Gc / 8.0 * (float(node_area(mesh) @ d) / l0 + l0 * float(d @ (K @ d)))
+    return e_kin, e_el, e_fr
