@@ -108,16 +108,21 @@ def kkt_residuals(A, b, lb, x):
     return viol, rf, ra
 
 
-def solve_bound_qp(A, b, lb, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9):
+def solve_bound_qp(A, b, lb, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9,
+                   kkt_tol: float = 1e-13):
     """Exact minimiser of 1/2 x'Ax - b'x subject to x >= lb.
 
     Primal-dual active set: with the multiplier mu = A x - b, a node is
     active when mu_i - A_ii (x_i - lb_i) > 0; free nodes solve
-    A_FF x_F = b_F - A_FA lb_A exactly.  Stops when the active set repeats.
-    Returns (x, active mask).
+    A_FF x_F = b_F - A_FA lb_A exactly.  The iteration stops as soon as the
+    iterate satisfies the KKT conditions to rounding (free nodes not below
+    their bound by more than kkt_tol, scaled multipliers mu_i/A_ii of active
+    nodes not below -kkt_tol), or when the active set repeats.  Nodes at a
+    degenerate free boundary (x_i = lb_i and mu_i = 0, e.g. the edge of the
+    AT1 support) would otherwise flip between the two sets on rounding noise.
+    Returns (x, active mask) with x >= lb.
     """
     A = sp.csr_matrix(A)
-    n = len(b)
     lb = np.asarray(lb, dtype=np.float64)
     dg = A.diagonal()
     x = np.maximum(lb if x0 is None else np.asarray(x0, dtype=np.float64), lb)
@@ -137,12 +142,15 @@ def solve_bound_qp(A, b, lb, x0=None, max_iter: int = 200, check: bool = True, t
             x[free] = spla.spsolve(Aff, rhs) if free.sum() > 1 else rhs / Aff.toarray()[0, 0]
         mu = A @ x - b
         mu[free] = 0.0
+        if np.all(x[free] >= lb[free] - kkt_tol) and np.all(mu[act] / dg[act] >= -kkt_tol):
+            break
         new_act = (mu - dg * (x - lb)) > 0
         if np.array_equal(new_act, act):
             break
         act = new_act
     else:
         raise RuntimeError("active-set iteration did not converge")
+    x = np.maximum(x, lb)
     if check:
         viol, rf, ra = kkt_residuals(A, b, lb, x)
         if viol > 0 or rf > tol or ra > tol:

@@ -202,3 +202,22 @@ def test_qp_tangent_by_finite_differences():
         dm = qp.solve(H - eps * dH, GC - eps * 0.3, lb - eps * dlb)[0]
         fd = (dp - dm) / (2 * eps)
         assert np.max(np.abs(fd - t)) < 1e-6 * max(1.0, np.abs(t).max())
+
+
+def test_at1_degenerate_free_boundary_early_steps():
+    """AT1 with sub-threshold history: the support edge is degenerate (d = lb, mu = 0).
+
+    The active-set iteration must still return the KKT point there; this
+    plate's second step used to make it flip nodes on rounding noise.
+    """
+    from oracle.step import Sim, initial_state
+    p = w.small_plate(48, 24, jitter=0.1, seed=2, model=1, split="starconvex", gamma_star=1.0, plane="stress")
+    sim = Sim(p)
+    st = initial_state(p)
+    for _ in range(4):
+        u1, v1, a1, H1, _ = sim.explicit(st)
+        A, b = sim.qp.system(H1.numpy(), p.Gc)
+        x, act = solve_bound_qp(A, b, st.d.numpy(), x0=st.d.numpy())
+        viol, rf, ra = kkt_residuals(A, b, st.d.numpy(), x)
+        assert viol <= 0 and rf < 1e-12 and ra < 1e-12
+        st = sim.step(st)
