@@ -1,0 +1,254 @@
+/*
+ * pf.h -- C ABI of libpfrac, an explicit-dynamics phase-field fracture step
+ * on 2D linear-triangle (P1) meshes for AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the matrix-free explicit phase-field method of
+ * "A matrix-free, differentiable PyTorch solver for phase-field fracture"
+ * (arXiv 2606.23458):
+ *   - pf_mesh_create    P1 geometry and lumped mass precomputed once
+ *                       (Sec. 2.3, eq. grad_phi and the lumped mass m_i);
+ *   - pf_explicit_step  velocity-Verlet predictor, strain, energy split with
+ *                       degradation g(d), internal force, corrector and the
+ *                       history maximum (Sec. 2.1-2.3, eq. spectral_split,
+ *                       eq. amor_split, eq. vv_u, eq. vv_a, eq. vv_v);
+ *   - pf_damage_solve   the bound-constrained AT1/AT2 damage update by a
+ *                       matrix-free projected preconditioned CG (Sec. 2.2,
+ *                       eq. damage_pde_at2, eq. damage_pde_at1; Sec. 2.4);
+ *   - pf_step_backward  the reverse (adjoint) of one staggered step, with
+ *                       the damage solve differentiated implicitly
+ *                       (Sec. 4.2, eq. implicit_adjoint_linear_system,
+ *                       eq. implicit_gc_l0_element_term).
+ *
+ * Conventions shared by every entry point
+ *   - Units are whatever the caller uses consistently (SI in the tests).
+ *   - A mesh handle holds one or more independent instances ("batched"
+ *     mode); n_instances = 1 is the plain case and takes the same path.
+ *   - Device arrays are caller-owned, contiguous, of the mesh dtype (float
+ *     for PF_F32, double for PF_F64) unless stated otherwise, and aligned
+ *     to at least 16 bytes.  Node arrays have n_nodes_total entries in the
+ *     mesh's INTERNAL node order; element arrays (the history H) have
+ *     n_elems_total entries in the INTERNAL element order.  pf_mesh_node_perm
+ *     and pf_mesh_elem_perm give the map from internal to the caller's ids.
+ *     Instances occupy contiguous ranges (pf_mesh_instance).
+ *   - Every entry point validates its arguments on the host first; on an
+ *     argument error nothing is enqueued and PF_ERR_ARG is returned.
+ *   - Work is enqueued on the given HIP stream and runs asynchronously.
+ *     pf_damage_solve and pf_step_backward may synchronise that stream to
+ *     test convergence (see pf_cg_opts_t.check_every).
+ *   - None of pf_explicit_step, pf_damage_solve, pf_step_backward allocates
+ *     memory: the workspaces are allocated by pf_mesh_create.
+ *   - A handle is not safe for concurrent calls from several threads or
+ *     streams; one call at a time per handle.
+ *   - No C++ exception crosses this interface.  On a non-OK status,
+ *     pf_last_error() returns a thread-local message.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_mesh_s* pf_mesh_t;
+typedef void* pf_stream_t;   /* a hipStream_t; NULL is the null stream */
+
+typedef enum {
+    PF_OK = 0,
+    PF_ERR_ARG = 1,            /* invalid argument (null pointer, size, enum, aliasing) */
+    PF_ERR_MESH = 2,           /* invalid mesh (index out of range, zero-area triangle, unused node) */
+    PF_ERR_HIP = 3,            /* a HIP runtime call failed; see pf_last_error() */
+    PF_ERR_NOMEM = 4,          /* device or host allocation failed */
+    PF_ERR_NOT_CONVERGED = 5,  /* CG reached max_iter; the last iterate is written */
+    PF_ERR_NONFINITE = 6,      /* a non-finite value appeared in a CG reduction */
+    PF_ERR_UNSUPPORTED = 7     /* combination not supported (e.g. mixed splits in one handle) */
+} pf_status_t;
+
+typedef enum { PF_F32 = 0, PF_F64 = 1 } pf_dtype_t;
+
+enum { PF_AT1 = 1, PF_AT2 = 2 };
+enum { PF_SPLIT_NONE = 0, PF_SPLIT_SPECTRAL = 1, PF_SPLIT_VOLDEV = 2, PF_SPLIT_STARCONVEX = 3 };
+enum { PF_PLANE_STRAIN = 0, PF_PLANE_STRESS = 1 };
+enum { PF_BOUNDS_PROJECTED = 0, PF_BOUNDS_POSTCLAMP = 1 };
+
+/* stats.flags bits, and active_out bits */
+enum { PF_FLAG_NOT_CONVERGED = 1, PF_FLAG_NONFINITE = 2 };
+enum { PF_ACTIVE_LOWER = 1, PF_ACTIVE_UPPER = 2 };
+
+/* One instance's mesh, host memory, read only during pf_mesh_create. */
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_elems;
+    const double* xy;        /* [n_nodes][2] node coordinates */
+    const int32_t* tri;      /* [n_elems][3] 0-based node ids, either orientation */
+    const uint8_t* fixed;    /* [n_nodes][2] 1 = velocity-prescribed DOF; NULL = none */
+} pf_mesh_desc_t;
+
+/* Tile plan options; NULL selects the defaults. */
+typedef struct {
+    int32_t tile_nodes;      /* owned nodes per tile, 64..2048; 0 = default (512) */
+} pf_tile_opts_t;
+
+/* Material and model of one instance (Sec. 2.1-2.2).  Geometry-independent. */
+typedef struct {
+    double E, nu, rho;       /* Young's modulus, Poisson ratio, density */
+    double Gc, l0;           /* fracture energy, regularisation length */
+    double eta;              /* residual stiffness in g(d) = (1-d)^2 + eta */
+    double gamma_star;       /* star-convex parameter (split 3 only), >= 0 */
+    int32_t model;           /* PF_AT1 | PF_AT2 */
+    int32_t split;           /* PF_SPLIT_*; the same for every instance of a handle */
+    int32_t plane;           /* PF_PLANE_STRAIN | PF_PLANE_STRESS */
+    int32_t bounds;          /* PF_BOUNDS_PROJECTED | PF_BOUNDS_POSTCLAMP (AT2 only) */
+} pf_params_t;
+
+/* Device pointers to one state; node arrays [n_nodes_total], H [n_elems_total]. */
+typedef struct {
+    void *ux, *uy, *vx, *vy, *ax, *ay, *d, *H;
+} pf_state_t;
+
+typedef struct {
+    double tol;              /* stop when max_i |r_i|/A_ii <= tol on free nodes and
+                                max_i r_i/A_ii <= tol on nodes held at the bound */
+    int32_t max_iter;        /* matrix-vector products per solve, >= 1 */
+    int32_t check_every;     /* > 0: synchronise the stream every check_every CG
+                                rounds to stop early (the default path);
+                                0: enqueue exactly max_iter rounds and never
+                                synchronise (suitable for HIP-graph capture) */
+} pf_cg_opts_t;
+
+/* Per-instance solve statistics, written to DEVICE memory by the solve. */
+typedef struct {
+    int32_t iters;           /* matrix-vector products */
+    int32_t restarts;        /* active-set restarts */
+    int32_t n_active;        /* nodes held at the lower bound at exit */
+    int32_t flags;           /* PF_FLAG_* */
+    double resid;            /* final scaled residual measure */
+} pf_cg_stats_t;
+
+typedef struct {
+    int32_t node_offset, n_nodes;    /* internal node range of the instance */
+    int32_t elem_offset, n_elems;    /* internal element range of the instance */
+    int32_t tile_offset, n_tiles;
+    double h_min;                    /* min incircle diameter 4 A_e / perimeter (Sec. 2.3, CFL) */
+    double area;                     /* total area */
+} pf_instance_info_t;
+
+typedef struct {
+    int32_t n_instances, n_nodes, n_elems, n_tiles;
+    int32_t dtype;                   /* pf_dtype_t */
+    int32_t max_tile_nodes, max_tile_elems;
+    int32_t tile_elems_total;        /* element records incl. halo copies */
+    size_t device_bytes;             /* device memory held by the handle */
+} pf_mesh_totals_t;
+
+/*
+ * Build a handle from n_instances meshes (Sec. 2.3: X, T given; grad phi,
+ * A_e and the lumped mass m_i = rho sum A_e/3 are precomputed once in FP64
+ * and stored in the handle's dtype).  Triangles are reoriented
+ * counter-clockwise; a zero-area triangle, an index out of range or a node
+ * used by no triangle gives PF_ERR_MESH.  Nodes are renumbered into tiles
+ * of nearby nodes (recursive coordinate bisection) for the element kernels.
+ * Allocates every device buffer the handle needs; synchronous on `stream`.
+ * On success *out owns the handle (free it with pf_mesh_destroy).
+ */
+pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_instances, pf_dtype_t dtype,
+                           const pf_tile_opts_t* tile, pf_stream_t stream, pf_mesh_t* out);
+
+/* Release a handle and its device memory (synchronises the device first). NULL is ignored. */
+pf_status_t pf_mesh_destroy(pf_mesh_t m);
+
+pf_status_t pf_mesh_totals(pf_mesh_t m, pf_mesh_totals_t* out);
+pf_status_t pf_mesh_instance(pf_mesh_t m, int32_t inst, pf_instance_info_t* out);
+
+/* Host output [n_nodes_total]: internal node id -> the caller's node id within its instance. */
+pf_status_t pf_mesh_node_perm(pf_mesh_t m, int32_t* out);
+/* Host output [n_elems_total]: internal element id -> the caller's element id within its instance. */
+pf_status_t pf_mesh_elem_perm(pf_mesh_t m, int32_t* out);
+
+/*
+ * One explicit step (Sec. 2.2 staggered scheme, first half; Sec. 2.3):
+ *   u_{n+1} = u_n + dt v_n + dt^2/2 a_n                          (eq. vv_u)
+ *   eps_e = sym grad u_{n+1};  d_e = (d_0 + d_1 + d_2)/3 of d_n
+ *   sigma_e = g(d_e) sigma+(eps_e) + sigma-(eps_e),  g = (1-d)^2 + eta
+ *   f_int,i = sum over corners of A_e sigma_e grad phi_k, gathered per node
+ *             in a fixed order (no atomics: bitwise reproducible)
+ *   a_{n+1} = m^-1 (f_ext - f_int) on free DOFs, 0 on prescribed DOFs (eq. vv_a)
+ *   v_{n+1} = v_n + dt/2 (a_n + a_{n+1})                          (eq. vv_v)
+ *   H_{n+1} = psi+(eps_e) if psi+ > H_n else H_n  (one value per element)
+ * `p` and `dt` are host arrays with one entry per instance.  Reads in->{u,v,a,d,H};
+ * writes out->{u,v,a,H}; out->d is not touched.  `in` and `out` must not share
+ * any array.  f_ext is a device array [2][n_nodes_total] (x block, then y
+ * block) or NULL for no external force.  Prescribed DOFs keep their
+ * velocity (a must be 0 there in `in`).
+ */
+pf_status_t pf_explicit_step(pf_mesh_t m, const pf_params_t* p, const double* dt,
+                             const pf_state_t* in, pf_state_t* out, const void* f_ext,
+                             pf_stream_t stream);
+
+/*
+ * Damage update (Sec. 2.2, eq. damage_pde_at2 / eq. damage_pde_at1; Sec. 2.4):
+ * the minimiser of 1/2 d'Ad - b'd subject to d >= d_prev, then d = min(d, 1), with
+ *   AT2: A = Gc l0 K + sum_e (Gc/l0 + 2 H_e) M^e,  b_i = sum 2 H_e A_e/3
+ *   AT1: A = 3/4 Gc l0 K + sum_e 2 H_e M^e,        b_i = sum (2 H_e - 3 Gc/(8 l0)) A_e/3
+ * K^e = A_e grad phi grad phi', consistent mass M^e_kl = A_e (1 + delta_kl)/12.
+ * Solved matrix-free by Jacobi-preconditioned projected CG warm-started from
+ * d_prev; in PF_BOUNDS_POSTCLAMP mode (AT2) the CG is unconstrained and the
+ * result is clamped to [d_prev, 1].
+ * H: device [n_elems_total]; d_prev: device [n_nodes_total]; d: device output
+ * [n_nodes_total] (must not alias d_prev).  active_out: device uint8
+ * [n_nodes_total] (PF_ACTIVE_* bits) or NULL.  stats: device array of
+ * n_instances pf_cg_stats_t, or NULL.  Returns PF_ERR_NOT_CONVERGED /
+ * PF_ERR_NONFINITE only when check_every > 0 (otherwise read stats.flags);
+ * the last iterate is written in every case.
+ */
+pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const void* H, const void* d_prev,
+                            void* d, uint8_t* active_out, const pf_cg_opts_t* opts,
+                            pf_cg_stats_t* stats, pf_stream_t stream);
+
+/*
+ * Reverse of one staggered step n -> n+1 (explicit step then damage solve).
+ * Given the forward states s_n, s_np1 and active_np1 (the active_out of the
+ * solve that produced s_np1->d), and the adjoints of s_np1 in adj_np1
+ * (u, v, a, d, H), writes the adjoints of s_n into adj_n and adds
+ * dL/dGc to dGc[inst] (device double, one per instance).  The damage solve
+ * is differentiated implicitly: one adjoint CG solve with the same operator
+ * restricted to the free nodes (Sec. 4.2), the Gc term
+ * -(l0 lambda'K d + lambda'M d / l0) for AT2 (eq. implicit_gc_l0_element_term)
+ * and its AT1 counterpart; nodes held at d_prev pass their adjoint to d_prev.
+ * adj_np1 is read only; adj_n must not alias adj_np1, s_n or s_np1.
+ */
+pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt,
+                             const pf_state_t* s_n, const pf_state_t* s_np1,
+                             const uint8_t* active_np1, const pf_state_t* adj_np1,
+                             pf_state_t* adj_n, double* dGc, const pf_cg_opts_t* opts,
+                             pf_cg_stats_t* stats, pf_stream_t stream);
+
+/*
+ * CFL time step of every instance (Sec. 2.3): dt_k = factor * h_min,k / c_p,k
+ * with c_p = sqrt((lambda + 2 mu)/rho) and lambda of the instance's plane.
+ * dt_out is a host array of n_instances doubles.
+ */
+pf_status_t pf_cfl_dt(pf_mesh_t m, const pf_params_t* p, double factor, double* dt_out);
+
+/* Thread-local description of the last non-OK status on this thread. */
+const char* pf_last_error(void);
+
+/* Library version string. */
+const char* pf_version(void);
+
+/*
+ * Kernel timing: when enabled, every kernel launch of this handle is
+ * bracketed by HIP events on its stream.  pf_timer_read synchronises the
+ * stream, returns the summed milliseconds and launch count of one kernel
+ * family (0 explicit step, 1 damage matvec, 2 damage update, 3 adjoint)
+ * and resets that family.
+ */
+pf_status_t pf_timer_enable(pf_mesh_t m, int32_t on);
+pf_status_t pf_timer_read(pf_mesh_t m, int32_t family, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -1,0 +1,9 @@
+"""MI355X-native matrix-free explicit phase-field fracture (libpfrac + Python binding).
+
+The hot path (explicit step, damage solve, adjoint step) runs in hand-written
+HIP kernels for gfx950 in libpfrac.so; this package marshals arguments to it.
+"""
+from . import _lib
+from .sim import CgConfig, Mesh, Simulator, State, params_of
+
+__all__ = ["_lib", "CgConfig", "Mesh", "Simulator", "State", "params_of"]

@@ -1,0 +1,108 @@
+// Device helpers shared by the kernels: state pointer bundles, deterministic
+// block reductions (wave64 butterflies, then a fixed-order combine of the
+// four waves) and the "last block of an instance" arrival test.
+#pragma once
+
+#include "pf_internal.hpp"
+
+namespace pf {
+
+template <typename T>
+struct StateIn {
+  const T* __restrict__ ux; const T* __restrict__ uy;
+  const T* __restrict__ vx; const T* __restrict__ vy;
+  const T* __restrict__ ax; const T* __restrict__ ay;
+  const T* __restrict__ d;  const T* __restrict__ H;
+};
+
+template <typename T>
+struct StateOut {
+  T* __restrict__ ux; T* __restrict__ uy;
+  T* __restrict__ vx; T* __restrict__ vy;
+  T* __restrict__ ax; T* __restrict__ ay;
+  T* __restrict__ d;  T* __restrict__ H;
+};
+
+template <typename T>
+inline StateIn<T> state_in(const pf_state_t* s) {
+  return StateIn<T>{(const T*)s->ux, (const T*)s->uy, (const T*)s->vx, (const T*)s->vy,
+                    (const T*)s->ax, (const T*)s->ay, (const T*)s->d, (const T*)s->H};
+}
+
+template <typename T>
+inline StateOut<T> state_out(pf_state_t* s) {
+  return StateOut<T>{(T*)s->ux, (T*)s->uy, (T*)s->vx, (T*)s->vy, (T*)s->ax, (T*)s->ay, (T*)s->d, (T*)s->H};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide reductions; every thread gets the result.  `sh` holds kWaves doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = sh[0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) s += sh[k];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = sh[0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) s = fmax(s, sh[k]);
+  return s;
+}
+
+__device__ __forceinline__ double block_min(double v, double* sh) {
+  v = wave_min(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = sh[0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) s = fmin(s, sh[k]);
+  return s;
+}
+
+// Publish this block's partials (already stored by thread 0) and report
+// whether it is the last block of its instance to arrive.  Uses one integer
+// atomic per block; the caller resets the counter in the last block.
+__device__ __forceinline__ bool arrive_last(uint32_t* counter, int ntiles, int* sflag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
+    *sflag = (prev == uint32_t(ntiles - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *sflag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+}  // namespace pf

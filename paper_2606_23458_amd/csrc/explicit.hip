@@ -1,0 +1,188 @@
+// Explicit step (Sec. 2.2-2.3): velocity-Verlet predictor, P1 strain, energy
+// split with degradation, element forces, deterministic node gather,
+// corrector and the history maximum -- fused into one tile kernel.
+//
+// One workgroup per tile.  Phase 1 forms the predictor u* = u + dt v + dt^2/2 a
+// for the tile's owned and halo nodes in LDS (owned nodes also write u_{n+1}).
+// Phase 2 evaluates every element touching an owned node and stores its three
+// corner forces in LDS; owned elements also update H.  Phase 3 sums, for each
+// owned node, its corner forces in ascending element order (no atomics, so
+// the result is bitwise reproducible) and applies the corrector.
+#include "device_common.hpp"
+#include "split.hpp"
+
+namespace pf {
+
+template <typename T, int S, int NPT>
+__global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> in,
+                                                     StateOut<T> out, const T* __restrict__ fext) {
+  const TileRec t = dm.tiles[blockIdx.x];
+  const InstP<T> P = ip[t.inst];
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nloc = t.n_own + t.n_halo;
+  T* sux = reinterpret_cast<T*>(smem);
+  T* suy = sux + nloc;
+  T* sd = suy + nloc;
+  T* sfx = sd + nloc;
+  T* sfy = sfx + 3 * t.n_telem;
+  const int tid = threadIdx.x;
+
+  // ---- phase 1: predictor (eq. vv_u) -------------------------------------
+  T rvx[NPT], rvy[NPT], rax[NPT], ray[NPT];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * kBlock;
+    if (i < t.n_own) {
+      const int g = t.node_begin + i;
+      const T vx = in.vx[g], vy = in.vy[g], ax = in.ax[g], ay = in.ay[g];
+      const T usx = in.ux[g] + P.dt * vx + P.half_dt2 * ax;
+      const T usy = in.uy[g] + P.dt * vy + P.half_dt2 * ay;
+      sux[i] = usx;
+      suy[i] = usy;
+      sd[i] = in.d[g];
+      out.ux[g] = usx;
+      out.uy[g] = usy;
+      rvx[r] = vx, rvy[r] = vy, rax[r] = ax, ray[r] = ay;
+    }
+  }
+  for (int i = t.n_own + tid; i < nloc; i += kBlock) {
+    const int g = dm.halo_idx[t.halo_begin + (i - t.n_own)];
+    sux[i] = in.ux[g] + P.dt * in.vx[g] + P.half_dt2 * in.ax[g];
+    suy[i] = in.uy[g] + P.dt * in.vy[g] + P.half_dt2 * in.ay[g];
+    sd[i] = in.d[g];
+  }
+  __syncthreads();
+
+  // ---- phase 2: element strain, split, stress, corner forces, history ------
+  const T* __restrict__ geo = static_cast<const T*>(dm.geo);
+  const size_t nte = size_t(dm.n_te);
+  for (int e = tid; e < t.n_telem; e += kBlock) {
+    const int te = t.telem_begin + e;
+    const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
+    const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+    const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+    const T u0x = sux[c0], u0y = suy[c0], u1x = sux[c1], u1y = suy[c1], u2x = sux[c2], u2y = suy[c2];
+    T exx, eyy, exy;
+    elem_strain<T>(u0x, u0y, u1x, u1y, u2x, u2y, g0x, g0y, g1x, g1y, g2x, g2y, exx, eyy, exy);
+    T psi_p, sp[3], sm[3];
+    split_eval<S, T>(exx, eyy, exy, P, psi_p, sp, sm);
+    const T de = (sd[c0] + sd[c1] + sd[c2]) / T(3);
+    const T om = T(1) - de;
+    const T gd = om * om + P.eta;
+    const T sxx = gd * sp[0] + sm[0], syy = gd * sp[1] + sm[1], sxy = gd * sp[2] + sm[2];
+    sfx[3 * e + 0] = A * (sxx * g0x + sxy * g0y);
+    sfy[3 * e + 0] = A * (sxy * g0x + syy * g0y);
+    sfx[3 * e + 1] = A * (sxx * g1x + sxy * g1y);
+    sfy[3 * e + 1] = A * (sxy * g1x + syy * g1y);
+    sfx[3 * e + 2] = A * (sxx * g2x + sxy * g2y);
+    sfy[3 * e + 2] = A * (sxy * g2x + syy * g2y);
+    if (e < t.n_own_elem) {
+      const int gid = t.own_elem_begin + e;
+      const T Hn = in.H[gid];
+      out.H[gid] = psi_p > Hn ? psi_p : Hn;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 3: gather f_int, corrector (eq. vv_a, eq. vv_v) ---------------
+  const T* __restrict__ invw = static_cast<const T*>(dm.inv_w);
+  const size_t N = size_t(dm.n_nodes);
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * kBlock;
+    if (i < t.n_own) {
+      const int g = t.node_begin + i;
+      const int j0 = dm.lrow[g], j1 = dm.lrow[g + 1];
+      T fx = T(0), fy = T(0);
+      for (int j = j0; j < j1; ++j) {
+        const int c = dm.lcorner[j];
+        fx += sfx[c];
+        fy += sfy[c];
+      }
+      const T minv = P.inv_rho * invw[g];
+      const uint8_t fl = dm.fixed[g];
+      const T ex = fext ? fext[g] : T(0);
+      const T ey = fext ? fext[N + g] : T(0);
+      const T axn = (fl & 1) ? T(0) : minv * (ex - fx);
+      const T ayn = (fl & 2) ? T(0) : minv * (ey - fy);
+      out.vx[g] = rvx[r] + P.half_dt * (rax[r] + axn);
+      out.vy[g] = rvy[r] + P.half_dt * (ray[r] + ayn);
+      out.ax[g] = axn;
+      out.ay[g] = ayn;
+    }
+  }
+}
+
+template <typename T, int S>
+static hipError_t launch_explicit_s(pf_mesh_s* m, const pf_state_t* in, pf_state_t* out, const void* fext,
+                                    hipStream_t s) {
+  const int npt = (m->max_own + kBlock - 1) / kBlock;
+  const size_t lds = m->max_lds_explicit;
+  const InstP<T>* ip = static_cast<const InstP<T>*>(m->dw.instp);
+  auto si = state_in<T>(in);
+  auto so = state_out<T>(out);
+  const T* fe = static_cast<const T*>(fext);
+  dim3 grid(m->n_tiles), block(kBlock);
+  if (npt <= 1)
+    hipLaunchKernelGGL((k_explicit<T, S, 1>), grid, block, lds, s, m->dm, ip, si, so, fe);
+  else if (npt <= 2)
+    hipLaunchKernelGGL((k_explicit<T, S, 2>), grid, block, lds, s, m->dm, ip, si, so, fe);
+  else if (npt <= 4)
+    hipLaunchKernelGGL((k_explicit<T, S, 4>), grid, block, lds, s, m->dm, ip, si, so, fe);
+  else
+    hipLaunchKernelGGL((k_explicit<T, S, 8>), grid, block, lds, s, m->dm, ip, si, so, fe);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_explicit(pf_mesh_s* m, int split, const pf_state_t* in, pf_state_t* out, const void* fext,
+                                  hipStream_t s) {
+  switch (split) {
+    case SPLIT_NONE: return launch_explicit_s<T, SPLIT_NONE>(m, in, out, fext, s);
+    case SPLIT_SPECTRAL: return launch_explicit_s<T, SPLIT_SPECTRAL>(m, in, out, fext, s);
+    case SPLIT_VOLDEV: return launch_explicit_s<T, SPLIT_VOLDEV>(m, in, out, fext, s);
+    default: return launch_explicit_s<T, SPLIT_STAR>(m, in, out, fext, s);
+  }
+}
+
+pf_status_t check_state(const pf_state_t* s, bool need_d, bool need_H, const char* name) {
+  if (!s) return fail(PF_ERR_ARG, std::string(name) + " is NULL");
+  const void* p[] = {s->ux, s->uy, s->vx, s->vy, s->ax, s->ay};
+  for (const void* q : p)
+    if (!q) return fail(PF_ERR_ARG, std::string(name) + " has a NULL array");
+  if (need_d && !s->d) return fail(PF_ERR_ARG, std::string(name) + ".d is NULL");
+  if (need_H && !s->H) return fail(PF_ERR_ARG, std::string(name) + ".H is NULL");
+  return PF_OK;
+}
+
+bool states_share(const pf_state_t* a, const pf_state_t* b) {
+  const void* pa[] = {a->ux, a->uy, a->vx, a->vy, a->ax, a->ay, a->d, a->H};
+  const void* pb[] = {b->ux, b->uy, b->vx, b->vy, b->ax, b->ay, b->d, b->H};
+  for (const void* x : pa)
+    for (const void* y : pb)
+      if (x && x == y) return true;
+  return false;
+}
+
+}  // namespace pf
+
+using namespace pf;
+
+extern "C" pf_status_t pf_explicit_step(pf_mesh_t m, const pf_params_t* p, const double* dt, const pf_state_t* in,
+                                        pf_state_t* out, const void* f_ext, pf_stream_t stream) {
+  if (!m) return fail(PF_ERR_ARG, "mesh is NULL");
+  pf_status_t st;
+  if ((st = check_params(m, p, dt, true)) != PF_OK) return st;
+  if ((st = check_state(in, true, true, "in")) != PF_OK) return st;
+  if ((st = check_state(out, false, true, "out")) != PF_OK) return st;
+  if (states_share(in, out)) return fail(PF_ERR_ARG, "in and out share an array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  m->dt_cache.assign(dt, dt + m->n_inst);
+  if ((st = upload_params(m, p, dt, s)) != PF_OK) return st;
+  timer_begin(m, 0, s);
+  hipError_t e = (m->dtype == PF_F64) ? launch_explicit<double>(m, p[0].split, in, out, f_ext, s)
+                                      : launch_explicit<float>(m, p[0].split, in, out, f_ext, s);
+  timer_end(m, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "k_explicit launch");
+  return PF_OK;
+}

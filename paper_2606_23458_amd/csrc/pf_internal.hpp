@@ -1,0 +1,161 @@
+// Internal data structures of libpfrac (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+
+namespace pf {
+
+constexpr int kBlock = 256;          // threads per workgroup of every tile kernel (4 wave64s)
+constexpr int kMaxTileNodes = 2048;  // owned nodes per tile, upper limit
+constexpr int kWaves = kBlock / 64;
+
+// One tile: a contiguous range of owned nodes plus the halo needed to
+// evaluate every element that touches them.  Owned elements come first in
+// the tile's element list and carry consecutive internal element ids.
+struct TileRec {
+  int32_t node_begin;      // first owned node (internal id)
+  int32_t n_own;           // owned nodes
+  int32_t halo_begin;      // offset into halo_idx
+  int32_t n_halo;          // halo nodes (local ids n_own .. n_own+n_halo-1)
+  int32_t telem_begin;     // offset into the tile-element arrays
+  int32_t n_telem;         // elements evaluated by this tile (owned + halo)
+  int32_t n_own_elem;      // owned elements (first n_own_elem of the list)
+  int32_t own_elem_begin;  // internal id of the first owned element
+  int32_t inst;            // instance
+  int32_t lds_bytes;       // dynamic LDS this tile needs (explicit kernel, FP64 upper bound)
+  int32_t pad0, pad1;
+};
+
+// Per-instance constants for the kernels, in the arithmetic type T.
+template <typename T>
+struct InstP {
+  // explicit step
+  T dt, half_dt, half_dt2, inv_rho;
+  T lam, mu, Kc2, coef, gamma, eta;
+  // damage system scaled by s = l0/Gc:  A~ = kap K + sum (c0 + cH H_e) M^e,
+  // b~_i = sum (b0 + bH H_e) A_e/3
+  T kap, c0, cH, b0, bH;
+  // d(scaled operator)/dGc terms for the adjoint, scaled by 1/Gc (see adjoint.hip)
+  T gK, gM, gW;            // dL/dGc += -lam~'(gK K d + gM M d + gW w)
+  T tol;
+  int32_t model, bounds, split, pad;
+};
+
+// CG control block of one instance, in device memory.  Fields are read by
+// every block at kernel start and written only by the instance's last block.
+struct Ctl {
+  int32_t mode;       // 0 restart pending, 1 iterate, 2 done
+  int32_t setup;      // 1 on the first restart of a solve (assemble b and the diagonal)
+  int32_t release;    // the pending restart may release nodes held at the bound
+  int32_t hit;        // the current step is cut by a bound
+  int32_t iters, restarts, flags, nact;
+  int32_t pbuf;       // which search-direction buffer holds the current p
+  int32_t ntiles;     // tiles of this instance
+  int32_t tile0;      // first tile of this instance
+  int32_t pad0;
+  uint32_t cnt_a, cnt_b, cnt_c, pad1;   // arrival counters of the last-block reductions
+  double rz, alpha, beta, amax, resid, pq;
+  double ref;         // scale of the stopping test (1 for the damage QP, max |b_i|/A_ii for linear solves)
+  double pad2;
+};
+
+enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2 };
+
+// Device view of a mesh handle.
+struct DevMesh {
+  const TileRec* tiles;
+  const int32_t* halo_idx;      // [sum n_halo] internal node ids
+  const uint16_t* lc0;          // [n_te] local node index of corner 0/1/2
+  const uint16_t* lc1;
+  const uint16_t* lc2;
+  const int32_t* te_gid;        // [n_te] internal element id of each tile element
+  const void* geo;              // [7][n_te] gx0 gy0 gx1 gy1 gx2 gy2 area (mesh dtype)
+  const int32_t* lrow;          // [N+1] corner list range of each owned node
+  const uint16_t* lcorner;      // [sum] tile-local corner id 3*e+k, ascending element id
+  const void* inv_w;            // [N] 1 / sum_{e ni i} A_e/3 (mesh dtype)
+  const void* wlump;            // [N] sum_{e ni i} A_e/3 (mesh dtype)
+  const uint8_t* fixed;         // [N] bit0 x prescribed, bit1 y prescribed
+  int32_t n_nodes, n_elems, n_tiles, n_te;
+};
+
+// Device workspaces of the damage solve and of the adjoint.
+struct DevWork {
+  void* b; void* dinv; void* r; void* z; void* p0; void* p1; void* q;
+  uint8_t* wset;
+  void* lam; void* t0; void* t1;     // adjoint scratch vectors
+  void* hbar;                        // [n_elems] adjoint of H_{n+1} (adjoint step scratch)
+  double* part;                      // [n_tiles][8] block partials
+  Ctl* ctl;                          // [n_inst]
+  void* instp;                       // [n_inst] InstP<T>
+};
+
+struct Timer {
+  std::vector<hipEvent_t> ev;        // pairs
+  size_t used = 0;
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+
+}  // namespace pf
+
+struct pf_mesh_s {
+  pf_dtype_t dtype;
+  int32_t n_inst = 0, n_nodes = 0, n_elems = 0, n_tiles = 0, n_te = 0;
+  int32_t max_tile_nodes = 0, max_tile_elems = 0, max_own = 0, max_lds_explicit = 0, max_lds_damage = 0;
+  int32_t split = -1;
+  std::vector<pf_instance_info_t> info;
+  std::vector<int32_t> node_perm, elem_perm;
+  std::vector<pf::TileRec> tiles_h;
+  pf::DevMesh dm{};
+  pf::DevWork dw{};
+  std::vector<void*> allocs;         // every device allocation, freed at destroy
+  size_t device_bytes = 0;
+  // host mirror of the current per-instance parameters (bytes of InstP<T>[n_inst])
+  std::vector<unsigned char> instp_host;
+  std::vector<double> dt_cache;      // dt of the last explicit step (the damage solve reuses it)
+  pf::Ctl* ctl_pinned = nullptr;     // pinned host copy of the control blocks
+  bool timing = false;
+  pf::Timer timers[4];
+};
+
+namespace pf {
+
+void set_error(const std::string& s);
+pf_status_t fail(pf_status_t st, const std::string& s);
+pf_status_t hip_fail(hipError_t e, const char* what);
+
+#define PF_HIP(call)                                          \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return ::pf::hip_fail(e_, #call);   \
+  } while (0)
+
+// Fill the per-instance constants for dtype T; uploads them if they changed.
+pf_status_t upload_params(pf_mesh_s* m, const pf_params_t* p, const double* dt, hipStream_t s);
+
+// Kernel timing around launches.
+void timer_begin(pf_mesh_s* m, int family, hipStream_t s);
+void timer_end(pf_mesh_s* m, int family, hipStream_t s);
+
+inline size_t elem_size(pf_dtype_t t) { return t == PF_F64 ? 8 : 4; }
+
+pf_status_t check_params(const pf_mesh_s* m, const pf_params_t* p, const double* dt, bool need_dt);
+
+// Matrix-free CG on the damage operator (damage.hip).  kind 0: the bound-
+// constrained damage update (b assembled from H, lower bound lb, result in x).
+// kind 1: the linear system A_FF x_F = b_F on the fixed free set F = {W == 0}
+// (b, W and the starting x prepared by the caller in the workspaces; the
+// stopping test is relative to max |b_i|/A_ii).
+enum { CG_QP = 0, CG_LINEAR = 1 };
+pf_status_t damage_cg(pf_mesh_s* m, int kind, const void* H, const void* lb, void* x, uint8_t* active_out,
+                      const pf_cg_opts_t* o, pf_cg_stats_t* stats, hipStream_t s);
+pf_status_t check_state(const pf_state_t* s, bool need_d, bool need_H, const char* name);
+bool states_share(const pf_state_t* a, const pf_state_t* b);
+
+}  // namespace pf

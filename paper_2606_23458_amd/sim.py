@@ -1,0 +1,268 @@
+"""Python front end of libpfrac: mesh handles, device states and the staggered step.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libpfrac.  PyTorch provides device memory and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+NODE_FIELDS = ("ux", "uy", "vx", "vy", "ax", "ay", "d")
+
+
+def _stream(stream: torch.cuda.Stream | None = None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def torch_dtype(code: str) -> torch.dtype:
+    return {"f64": torch.float64, "f32": torch.float32}[code]
+
+
+class Mesh:
+    """A pf_mesh_t handle over one or more instances.
+
+    ``meshes`` are objects with ``xy`` (N,2) float64, ``tri`` (Ne,3) int and
+    ``fixed`` (N,2) uint8 arrays (for example workloads.Problem).
+    """
+
+    def __init__(self, meshes, dtype: str = "f64", tile_nodes: int = 0, device: str = "cuda"):
+        if dtype not in ("f32", "f64"):
+            raise ValueError(dtype)
+        self.dtype_code = dtype
+        self.dtype = torch_dtype(dtype)
+        self.device = torch.device(device)
+        n = len(meshes)
+        keep = []
+        descs = (L.MeshDesc * n)()
+        for k, pr in enumerate(meshes):
+            xy = np.ascontiguousarray(pr.xy, dtype=np.float64)
+            tri = np.ascontiguousarray(pr.tri, dtype=np.int32)
+            fx = None if getattr(pr, "fixed", None) is None else np.ascontiguousarray(pr.fixed, dtype=np.uint8)
+            keep += [xy, tri, fx]
+            descs[k] = L.MeshDesc(len(xy), len(tri), xy.ctypes.data, tri.ctypes.data,
+                                  None if fx is None else fx.ctypes.data)
+        h = C.c_void_p()
+        opts = L.TileOpts(int(tile_nodes))
+        L.call("pf_mesh_create", descs, n, L.PF_F64 if dtype == "f64" else L.PF_F32, C.byref(opts),
+               _stream(), C.byref(h))
+        self.handle = h
+        tot = L.Totals()
+        L.call("pf_mesh_totals", h, C.byref(tot))
+        self.totals = tot
+        self.n_instances, self.n_nodes, self.n_elems = tot.n_instances, tot.n_nodes, tot.n_elems
+        self.info = []
+        for k in range(n):
+            inf = L.InstanceInfo()
+            L.call("pf_mesh_instance", h, k, C.byref(inf))
+            self.info.append(inf)
+        self.node_perm = np.empty(self.n_nodes, dtype=np.int32)
+        L.call("pf_mesh_node_perm", h, self.node_perm.ctypes.data)
+        self.elem_perm = np.empty(self.n_elems, dtype=np.int32)
+        L.call("pf_mesh_elem_perm", h, self.elem_perm.ctypes.data)
+        # internal position of every user node / element, per instance
+        self.node_pos, self.elem_pos = [], []
+        for inf in self.info:
+            o, m = inf.node_offset, inf.n_nodes
+            pos = np.empty(m, dtype=np.int64)
+            pos[self.node_perm[o:o + m]] = np.arange(o, o + m)
+            self.node_pos.append(pos)
+            o, m = inf.elem_offset, inf.n_elems
+            pos = np.empty(m, dtype=np.int64)
+            pos[self.elem_perm[o:o + m]] = np.arange(o, o + m)
+            self.elem_pos.append(pos)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().pf_mesh_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- layout helpers (user numbering <-> internal numbering) ---------------
+    def nodes_to_internal(self, per_inst) -> np.ndarray:
+        first = np.asarray(per_inst[0])
+        out = np.zeros((self.n_nodes,) + first.shape[1:], dtype=np.float64)
+        for k, a in enumerate(per_inst):
+            out[self.node_pos[k]] = np.asarray(a)
+        return out
+
+    def nodes_from_internal(self, arr) -> list:
+        a = arr.detach().cpu().numpy() if isinstance(arr, torch.Tensor) else np.asarray(arr)
+        return [a[pos] for pos in self.node_pos]
+
+    def elems_to_internal(self, per_inst) -> np.ndarray:
+        first = np.asarray(per_inst[0])
+        out = np.zeros((self.n_elems,) + first.shape[1:], dtype=np.float64)
+        for k, a in enumerate(per_inst):
+            out[self.elem_pos[k]] = np.asarray(a)
+        return out
+
+    def elems_from_internal(self, arr) -> list:
+        a = arr.detach().cpu().numpy() if isinstance(arr, torch.Tensor) else np.asarray(arr)
+        return [a[pos] for pos in self.elem_pos]
+
+
+class State:
+    """Device state: node fields (7, N) = u_x u_y v_x v_y a_x a_y d, and H (Ne)."""
+
+    def __init__(self, mesh: Mesh, nodes: torch.Tensor | None = None, H: torch.Tensor | None = None):
+        self.mesh = mesh
+        self.nodes = nodes if nodes is not None else torch.zeros((7, mesh.n_nodes), dtype=mesh.dtype,
+                                                                   device=mesh.device)
+        self.H = H if H is not None else torch.zeros(mesh.n_elems, dtype=mesh.dtype, device=mesh.device)
+
+    def ptrs(self) -> L.StatePtrs:
+        return L.StatePtrs(*[self.nodes[i].data_ptr() for i in range(7)], self.H.data_ptr())
+
+    def clone(self) -> "State":
+        return State(self.mesh, self.nodes.clone(), self.H.clone())
+
+    def copy_(self, other: "State") -> "State":
+        self.nodes.copy_(other.nodes)
+        self.H.copy_(other.H)
+        return self
+
+    def zero_(self) -> "State":
+        self.nodes.zero_()
+        self.H.zero_()
+        return self
+
+    @property
+    def d(self) -> torch.Tensor:
+        return self.nodes[6]
+
+    def to_user(self) -> list[dict]:
+        """Per instance: dict of numpy arrays u, v, a (N,2), d (N,), H (Ne,) in the caller's numbering."""
+        nodes = self.mesh.nodes_from_internal(self.nodes.double().T)
+        H = self.mesh.elems_from_internal(self.H.double())
+        out = []
+        for k in range(self.mesh.n_instances):
+            nd = nodes[k]
+            out.append({"u": nd[:, 0:2], "v": nd[:, 2:4], "a": nd[:, 4:6], "d": nd[:, 6], "H": H[k]})
+        return out
+
+    @staticmethod
+    def from_user(mesh: Mesh, per_inst: list[dict]) -> "State":
+        cols = [np.concatenate([np.asarray(s["u"]), np.asarray(s["v"]), np.asarray(s["a"]),
+                                np.asarray(s["d"])[:, None]], 1) for s in per_inst]
+        nodes = torch.tensor(mesh.nodes_to_internal(cols).T.copy(), dtype=mesh.dtype, device=mesh.device)
+        H = torch.tensor(mesh.elems_to_internal([np.asarray(s["H"]) for s in per_inst]), dtype=mesh.dtype,
+                         device=mesh.device)
+        return State(mesh, nodes.contiguous(), H)
+
+
+def params_of(problem, Gc: float | None = None) -> L.Params:
+    return L.Params(problem.E, problem.nu, problem.rho, problem.Gc if Gc is None else Gc, problem.l0, problem.eta,
+                    problem.gamma_star, int(problem.model), L.SPLITS[problem.split], L.PLANES[problem.plane],
+                    L.BOUNDS[getattr(problem, "bounds", "projected")])
+
+
+@dataclass
+class CgConfig:
+    tol: float = 1e-12
+    max_iter: int = 2000
+    check_every: int = 8
+
+    def opts(self) -> L.CgOpts:
+        return L.CgOpts(self.tol, self.max_iter, self.check_every)
+
+
+def default_tol(dtype: str) -> float:
+    return 1e-12 if dtype == "f64" else 1e-6
+
+
+class Simulator:
+    """Staggered explicit phase-field simulation of one or more instances on one GPU."""
+
+    def __init__(self, problems, dtype: str | None = None, tile_nodes: int = 0, cg: CgConfig | None = None,
+                 dt: list[float] | None = None, mesh: Mesh | None = None):
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        self.problems = list(problems)
+        self.dtype_code = dtype or self.problems[0].dtype
+        self.mesh = mesh or Mesh(self.problems, self.dtype_code, tile_nodes)
+        n = len(self.problems)
+        self.params = (L.Params * n)(*[params_of(p) for p in self.problems])
+        self.dt = (C.c_double * n)()
+        if dt is None:
+            cfl = self.problems[0].cfl
+            if any(p.cfl != cfl for p in self.problems):
+                raise ValueError("all instances of a simulator share one CFL factor")
+            L.call("pf_cfl_dt", self.mesh.handle, self.params, cfl, self.dt)
+        else:
+            for k, v in enumerate(dt):
+                self.dt[k] = float(v)
+        self.cg = cg or CgConfig(tol=default_tol(self.dtype_code))
+        self.stats = torch.zeros(n * 6, dtype=torch.int32, device=self.mesh.device)   # pf_cg_stats_t[n]
+        self.active = torch.zeros(self.mesh.n_nodes, dtype=torch.uint8, device=self.mesh.device)
+        self.state = self.initial_state()
+        self._next = State(self.mesh)
+        self.steps_done = 0
+
+    def set_Gc(self, values) -> None:
+        for k, v in enumerate(np.atleast_1d(values)):
+            self.params[k].Gc = float(v)
+
+    def initial_state(self) -> State:
+        return State.from_user(self.mesh, [{"u": p.u0, "v": p.v0, "a": p.a0, "d": p.d0, "H": p.H0}
+                                           for p in self.problems])
+
+    def reset(self) -> None:
+        self.state = self.initial_state()
+        self.steps_done = 0
+
+    # --- the two halves of the staggered step --------------------------------
+    def explicit(self, s_in: State, s_out: State, f_ext: torch.Tensor | None = None) -> None:
+        a, b = s_in.ptrs(), s_out.ptrs()
+        L.call("pf_explicit_step", self.mesh.handle, self.params, self.dt, C.byref(a), C.byref(b),
+               _ptr(f_ext), _stream())
+
+    def damage(self, H: torch.Tensor, d_prev: torch.Tensor, d_out: torch.Tensor,
+               active: torch.Tensor | None = None) -> None:
+        o = self.cg.opts()
+        L.call("pf_damage_solve", self.mesh.handle, self.params, H.data_ptr(), d_prev.data_ptr(), d_out.data_ptr(),
+               _ptr(active), C.byref(o), self.stats.data_ptr(), _stream())
+
+    def step_into(self, s_in: State, s_out: State, active: torch.Tensor | None = None) -> None:
+        self.explicit(s_in, s_out)
+        self.damage(s_out.H, s_in.d, s_out.d, active if active is not None else self.active)
+
+    def step(self, n: int = 1) -> State:
+        for _ in range(n):
+            self.step_into(self.state, self._next)
+            self.state, self._next = self._next, self.state
+            self.steps_done += 1
+        return self.state
+
+    def cg_stats(self) -> list[dict]:
+        raw = self.stats.cpu().numpy().view(np.int32).reshape(-1, 6)
+        out = []
+        for r in raw:
+            resid = np.frombuffer(r[4:6].tobytes(), dtype=np.float64)[0]
+            out.append({"iters": int(r[0]), "restarts": int(r[1]), "n_active": int(r[2]), "flags": int(r[3]),
+                        "resid": float(resid)})
+        return out
+
+    def timer(self, on: bool) -> None:
+        L.call("pf_timer_enable", self.mesh.handle, 1 if on else 0)
+
+    def timer_read(self, family: int) -> tuple[float, int]:
+        ms = C.c_double()
+        n = C.c_int64()
+        L.call("pf_timer_read", self.mesh.handle, family, C.byref(ms), C.byref(n))
+        return ms.value, n.value

@@ -1,0 +1,145 @@
+"""HIP path (through the C ABI) against the FP64 CPU oracle on seeded inputs.
+
+Tolerances: FP64 kernels agree with the oracle to 1e-12 relative on one step
+and 1e-9 relative over a full trajectory; FP32 kernels agree on damage to
+1e-4 (absolute, damage is in [0, 1]) and on the mechanics to a relative error
+set by FP32 rounding (2e-5 over one step).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle.damage import DamageQP, assemble_damage, kkt_residuals
+from oracle.step import Sim as OSim, run as orun
+from tests.gpu_common import random_state, rel_err, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+SPLITS = ["none", "spectral", "voldev", "starconvex"]
+
+
+def _sim(problem, dtype, tile_nodes=64, **kw):
+    from paper_2606_23458_amd import Simulator
+    return Simulator(problem, dtype=dtype, tile_nodes=tile_nodes, **kw)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("plane", ["strain", "stress"])
+def test_explicit_step_matches_oracle(dtype, split, plane):
+    from paper_2606_23458_amd import State
+    p = w.small_plate(23, 13, jitter=0.2, seed=3, split=split, plane=plane, gamma_star=0.8, random_diag=True)
+    osim = OSim(p)
+    sim = _sim(p, dtype, dt=[osim.dt])
+    st = random_state(p, seed=11)
+    s_in = State.from_user(sim.mesh, [st])
+    s_out = State(sim.mesh)
+    sim.explicit(s_in, s_out)
+    torch.cuda.synchronize()
+    got = s_out.to_user()[0]
+    u1, v1, a1, H1, _ = osim.explicit(to_oracle(st))
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert rel_err(got["u"], u1.numpy()) < tol
+    assert rel_err(got["v"], v1.numpy()) < tol
+    assert rel_err(got["a"], a1.numpy()) < (tol if dtype == "f64" else 1e-3)
+    assert rel_err(got["H"], H1.numpy()) < (tol if dtype == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", [1, 2])
+def test_damage_solve_matches_exact_qp(dtype, model):
+    from paper_2606_23458_amd import State
+    p = w.small_plate(30, 16, jitter=0.15, seed=4, model=model, random_diag=True)
+    sim = _sim(p, dtype)
+    r = np.random.default_rng(5)
+    H = r.uniform(0, 8000.0, p.n_elems) * (r.random(p.n_elems) < 0.5)
+    lb = np.where(r.random(p.n_nodes) < 0.3, r.uniform(0, 0.9, p.n_nodes), 0.0)
+    lb[p.d0 == 1.0] = 1.0
+    st = {"u": np.zeros((p.n_nodes, 2)), "v": np.zeros((p.n_nodes, 2)), "a": np.zeros((p.n_nodes, 2)),
+          "d": lb, "H": H}
+    s_in = State.from_user(sim.mesh, [st])
+    d_out = torch.zeros_like(s_in.d)
+    sim.damage(s_in.H, s_in.d, d_out, sim.active)
+    torch.cuda.synchronize()
+    got = sim.mesh.nodes_from_internal(d_out.double())[0]
+    qp = DamageQP(OSim(p).mesh, p.l0, model)
+    ref, act, upper, x, A = qp.solve(H, p.Gc, lb)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    assert np.max(np.abs(got - ref)) < tol, sim.cg_stats()
+    assert np.all(got >= lb - (0 if dtype == "f64" else 1e-7)) and np.all(got <= 1.0)
+    if dtype == "f64":
+        act_gpu = sim.mesh.nodes_from_internal(sim.active.to(torch.int32))[0] & 1
+        # nodes strictly inside the feasible set must agree on being free
+        assert np.all(act_gpu[got > lb + 1e-8] == 0)
+    st_ = sim.cg_stats()[0]
+    assert st_["flags"] == 0 and st_["iters"] >= 1
+
+
+def test_damage_solve_postclamp_mode():
+    from paper_2606_23458_amd import State
+    p = w.small_plate(20, 12, jitter=0.15, seed=6, model=2).with_(bounds="postclamp")
+    sim = _sim(p, "f64")
+    r = np.random.default_rng(7)
+    H = r.uniform(0, 5000.0, p.n_elems)
+    lb = r.uniform(0, 0.6, p.n_nodes)
+    st = {"u": np.zeros((p.n_nodes, 2)), "v": np.zeros((p.n_nodes, 2)), "a": np.zeros((p.n_nodes, 2)),
+          "d": lb, "H": H}
+    s_in = State.from_user(sim.mesh, [st])
+    d_out = torch.zeros_like(s_in.d)
+    sim.damage(s_in.H, s_in.d, d_out, sim.active)
+    torch.cuda.synchronize()
+    got = sim.mesh.nodes_from_internal(d_out)[0]
+    qp = DamageQP(OSim(p).mesh, p.l0, 2, bounds="postclamp")
+    ref = qp.solve(H, p.Gc, lb)[0]
+    assert np.max(np.abs(got - ref)) < 1e-10
+
+
+def test_config0_trajectory_fp64():
+    """Full config-0 run (64x32, AT2/spectral/plane strain, 200 steps) against the oracle."""
+    p = w.config0()
+    ref, rec, osim = orun(p, steps=200, record_every=50)
+    sim = _sim(p, "f64", tile_nodes=0, dt=[osim.dt])
+    snaps = []
+    for k in range(4):
+        sim.step(50)
+        snaps.append(sim.state.to_user()[0])
+    for got, want in zip(snaps, rec):
+        assert rel_err(got["u"], want["u"]) < 1e-9
+        assert rel_err(got["v"], want["v"]) < 1e-9
+        assert np.max(np.abs(got["d"] - want["d"])) < 1e-9
+        assert rel_err(got["H"], want["H"]) < 1e-9
+
+
+@pytest.mark.parametrize("plane", ["strain", "stress"])
+def test_cfl_time_step_matches_oracle(plane):
+    """pf_cfl_dt: dt = 0.5 h_min / c_p (Sec. 2.3) from the library's own geometry."""
+    p = w.small_plate(31, 17, jitter=0.25, seed=8, plane=plane, random_diag=True)
+    sim = _sim(p, "f64")
+    assert abs(sim.dt[0] - OSim(p).dt) < 1e-14 * OSim(p).dt
+
+
+def test_runs_are_bitwise_reproducible():
+    p = w.small_plate(40, 20, model=1, split="voldev", seed=9).with_(steps=30)
+    outs = []
+    for _ in range(2):
+        sim = _sim(p, "f32", tile_nodes=128)
+        sim.step(30)
+        outs.append(sim.state.nodes.cpu().clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("model,split", [(2, "spectral"), (1, "starconvex"), (2, "voldev")])
+def test_staggered_steps_and_bounds(model, split):
+    """A short run in FP32 stays within 1e-4 of the oracle's damage and keeps the bounds."""
+    p = w.small_plate(48, 24, jitter=0.1, seed=2, model=model, split=split, gamma_star=1.0,
+                      plane="stress" if model == 1 else "strain").with_(steps=60)
+    ref, rec, osim = orun(p, steps=60, record_every=20)
+    sim = _sim(p, "f32", tile_nodes=128, dt=[osim.dt])
+    prev = sim.state.to_user()[0]["d"]
+    for k in range(3):
+        sim.step(20)
+        got = sim.state.to_user()[0]
+        assert np.max(np.abs(got["d"] - rec[k]["d"])) < 1e-4
+        assert np.all(got["d"] >= prev) and np.all(got["d"] <= 1.0)
+        prev = got["d"]
