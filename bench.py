@@ -1,0 +1,235 @@
+"""Benchmark of the explicit phase-field hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+
+Headline: full staggered steps (explicit step + damage solve) of the
+1024x512 plate (1,048,576 triangles, FP32 kernels, AT2 / vol-dev / plane
+strain), reported as element-steps per second with inputs resident in HBM.
+Also reported on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average launch time (HIP events around each launch);
+  cpu_baseline  the FP64 CPU oracle on one staggered step of the same plate;
+  bwd_fwd       backward/forward time of the checkpointed gradient on the
+                256x128 FP64 plate (500 steps, checkpoints every 50);
+  batched       simulations/s of one batched forward+backward evaluation of
+                the 64-plate inverse workload vs the same 64 evaluations one
+                plate at a time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per element and launch (paper layout: precomputed grad phi
+# and area, int32 connectivity and corner lists), per arithmetic width w.
+#   explicit step: nodes 14w + 4 (u, v, a read and written, m^-1, d, row
+#   pointer), elements 24 + 9w (connectivity, 6 grad phi + area, H read and
+#   written, 3 corner ids); with N ~ N_e/2 that is 90 B (w = 4), 154 B (w = 8).
+#   damage matvec (kernel A): nodes 4w (z, p_old read; p, q written),
+#   elements 8w + 24 (geometry, H, connectivity, corner ids).
+#   damage update (kernel B): nodes 9w (p, x, r, q, D^-1, lb read; x, r, z written).
+
+
+def alg_bytes_per_elem(family: int, w: int) -> float:
+    if family == 0:
+        return (14 * w + 4) / 2 + 24 + 9 * w
+    if family == 1:
+        return 4 * w / 2 + 8 * w + 24
+    if family == 2:
+        return 9 * w / 2
+    raise ValueError(family)
+
+
+FAMILY = {0: "k_explicit", 1: "k_dmg_a (damage matvec)", 2: "k_dmg_b (damage update)", 3: "adjoint",
+          4: "k_dmg_reduce (per-instance CG reductions)"}
+
+
+def gpu_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def run_headline(steps: int, warmup: int, tile_nodes: int):
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import Simulator
+
+    p = w.config1()
+    sim = Simulator(p, dtype="f32", tile_nodes=tile_nodes)
+    ne = sim.mesh.n_elems
+    sim.step(warmup)
+    gpu_sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    sim.step(steps)
+    ev1.record()
+    gpu_sync()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    # second pass with per-kernel events (same work) for the roofline
+    sim.timer(True)
+    for f in range(5):
+        sim.timer_read(f)
+    iters = []
+    for _ in range(steps):
+        sim.step()
+        iters.append(sim.cg_stats()[0]["iters"])
+    gpu_sync()
+    fam = {f: sim.timer_read(f) for f in (0, 1, 2, 4)}
+    sim.timer(False)
+    return {"sim": sim, "ne": ne, "ms": ms, "wall": wall, "fam": fam, "iters": iters, "problem": p}
+
+
+def roofline(res, w: int) -> dict:
+    ne = res["ne"]
+    fam = res["fam"]
+    dom = max((f for f in fam if f != 4), key=lambda f: fam[f][0])
+    tot_ms, launches = fam[dom]
+    avg_s = tot_ms / max(launches, 1) / 1e3
+    bytes_per_launch = alg_bytes_per_elem(dom, w) * ne
+    achieved = bytes_per_launch / avg_s / 1e9
+    out = {"bound": "hbm", "kernel": FAMILY[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+           "alg_bytes_per_launch": int(bytes_per_launch)}
+    out["per_kernel_us"] = {FAMILY[f]: round(fam[f][0] / max(fam[f][1], 1) * 1e3, 2) for f in fam}
+    out["share"] = {FAMILY[f]: round(fam[f][0] / sum(v[0] for v in fam.values()), 3) for f in fam}
+    return out
+
+
+def cpu_baseline() -> dict:
+    """The FP64 oracle, one thread, one staggered step of the 1024x512 plate."""
+    import torch
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    torch.set_num_threads(1)
+    import workloads as w
+    from oracle.step import Sim, initial_state
+    p = w.config1()
+    sim = Sim(p)
+    st = initial_state(p)
+    t0 = time.perf_counter()
+    st = sim.step(st)
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": round(p.n_elems / dt, 1), "unit": "elem-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "1 staggered step (explicit step + exact damage QP by sparse LU) of the 1024x512 plate "
+                      f"from its initial state, FP64, {dt:.1f} s"}
+
+
+def bwd_fwd_ratio() -> dict:
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import Simulator
+    from paper_2606_23458_amd.grad import TrajectoryRunner
+
+    p = w.config3()
+    sim = Simulator(p, dtype="f64")
+    runner = TrajectoryRunner(sim, steps=p.steps, checkpoint_every=50)
+    runner.forward()
+    gpu_sync()
+    t0 = time.perf_counter()
+    runner.forward()
+    gpu_sync()
+    t_fwd = time.perf_counter() - t0
+    dbar = torch.zeros(sim.mesh.n_nodes, dtype=torch.float64, device="cuda")
+    dbar.copy_(sim.state.d * (2.0 / sim.mesh.n_nodes))
+    t0 = time.perf_counter()
+    runner.backward(dbar)
+    gpu_sync()
+    t_bwd = time.perf_counter() - t0
+    return {"workload": "256x128 plate, FP64, AT2/spectral/plane strain, 500 steps, checkpoint every 50",
+            "fwd_s": round(t_fwd, 3), "bwd_s": round(t_bwd, 3), "ratio": round(t_bwd / t_fwd, 3),
+            "note": "bwd includes the checkpoint recompute"}
+
+
+def batched_vs_plain(n_inst: int = 64, steps: int = 300) -> dict:
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import Simulator
+    from paper_2606_23458_amd.grad import TrajectoryRunner
+
+    probs = w.config4(n_inst)
+    # batched: one handle, one forward + backward of all instances
+    sim = Simulator(probs, dtype="f32")
+    runner = TrajectoryRunner(sim, steps=steps, checkpoint_every=50)
+    gpu_sync()
+    t0 = time.perf_counter()
+    runner.forward()
+    dbar = sim.state.d * 1e-3
+    runner.backward(dbar)
+    gpu_sync()
+    t_b = time.perf_counter() - t0
+    # plain: the same evaluations one instance at a time
+    t_p = 0.0
+    for pr in probs:
+        s1 = Simulator([pr], dtype="f32")
+        r1 = TrajectoryRunner(s1, steps=steps, checkpoint_every=50)
+        gpu_sync()
+        t0 = time.perf_counter()
+        r1.forward()
+        r1.backward(s1.state.d * 1e-3)
+        gpu_sync()
+        t_p += time.perf_counter() - t0
+        del r1, s1
+    ne = sum(p.n_elems for p in probs)
+    return {"workload": f"{n_inst} plates 128x64..512x256 ({ne} triangles), FP32, {steps} steps fwd+bwd",
+            "batched_sims_per_s": round(n_inst / t_b, 3), "plain_sims_per_s": round(n_inst / t_p, 3),
+            "speedup": round(t_p / t_b, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--tile-nodes", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    res = run_headline(args.steps, args.warmup, args.tile_nodes)
+    ms_step = res["ms"] / args.steps
+    value = res["ne"] * args.steps / (res["ms"] / 1e3)
+    iters = res["iters"]
+    out = {
+        "metric": "elem-steps/s and % HBM peak; batched vs plain sims/s; bwd/fwd time ratio",
+        "value": round(value, 1), "unit": "elem-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "1024x512 jittered plate, 1048576 triangles, AT2 / vol-dev / plane strain, "
+                               "full staggered step (explicit + projected-CG damage solve)",
+                   "n_elems": res["ne"], "n_nodes": res["sim"].mesh.n_nodes, "precision": "fp32 kernels, fp64 CG reductions"},
+        "roofline": roofline(res, 4),
+        "cg_iters_per_solve": {"mean": round(sum(iters) / len(iters), 2), "max": max(iters)},
+    }
+    if not args.no_extras:
+        out["bwd_fwd"] = bwd_fwd_ratio()
+        out["batched"] = batched_vs_plain()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

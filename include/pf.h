@@ -189,23 +189,29 @@ pf_status_t pf_explicit_step(pf_mesh_t m, const pf_params_t* p, const double* dt
 
 /*
  * Damage update (Sec. 2.2, eq. damage_pde_at2 / eq. damage_pde_at1; Sec. 2.4):
- * the minimiser of 1/2 d'Ad - b'd subject to d >= d_prev, then d = min(d, 1), with
+ * the minimiser of 1/2 d'Ad - b'd subject to d_prev <= d <= 1, with
  *   AT2: A = Gc l0 K + sum_e (Gc/l0 + 2 H_e) M^e,  b_i = sum 2 H_e A_e/3
  *   AT1: A = 3/4 Gc l0 K + sum_e 2 H_e M^e,        b_i = sum (2 H_e - 3 Gc/(8 l0)) A_e/3
  * K^e = A_e grad phi grad phi', consistent mass M^e_kl = A_e (1 + delta_kl)/12.
  * Solved matrix-free by Jacobi-preconditioned projected CG warm-started from
- * d_prev; in PF_BOUNDS_POSTCLAMP mode (AT2) the CG is unconstrained and the
- * result is clamped to [d_prev, 1].
+ * d_prev: CG runs on the free nodes with the held nodes frozen at their
+ * bound, and the held set is updated between CG runs (primal-dual active-set
+ * steps, with a monotone projected-CG fallback) until the KKT conditions hold
+ * to tol.  Nodes with d_prev = 1 stay at 1.  In PF_BOUNDS_POSTCLAMP mode
+ * (AT2) the CG is unconstrained and the result is clamped to [d_prev, 1].
  * H: device [n_elems_total]; d_prev: device [n_nodes_total]; d: device output
- * [n_nodes_total] (must not alias d_prev).  active_out: device uint8
- * [n_nodes_total] (PF_ACTIVE_* bits) or NULL.  stats: device array of
- * n_instances pf_cg_stats_t, or NULL.  Returns PF_ERR_NOT_CONVERGED /
- * PF_ERR_NONFINITE only when check_every > 0 (otherwise read stats.flags);
- * the last iterate is written in every case.
+ * [n_nodes_total] (must not alias d_prev).  active_guess: device uint8
+ * [n_nodes_total] whose PF_ACTIVE_* bits seed the held set (normally the
+ * previous step's active_out), or NULL for an empty start; it only affects
+ * the iteration count and the result within tol.  active_out: device uint8
+ * [n_nodes_total] (PF_ACTIVE_* bits) or NULL; it may be the same array as
+ * active_guess.  stats: device array of n_instances pf_cg_stats_t, or NULL.
+ * Returns PF_ERR_NOT_CONVERGED / PF_ERR_NONFINITE only when check_every > 0
+ * (otherwise read stats.flags); the last iterate is written in every case.
  */
 pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const void* H, const void* d_prev,
-                            void* d, uint8_t* active_out, const pf_cg_opts_t* opts,
-                            pf_cg_stats_t* stats, pf_stream_t stream);
+                            void* d, const uint8_t* active_guess, uint8_t* active_out,
+                            const pf_cg_opts_t* opts, pf_cg_stats_t* stats, pf_stream_t stream);
 
 /*
  * Reverse of one staggered step n -> n+1 (explicit step then damage solve).
@@ -216,7 +222,9 @@ pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const void* H, co
  * is differentiated implicitly: one adjoint CG solve with the same operator
  * restricted to the free nodes (Sec. 4.2), the Gc term
  * -(l0 lambda'K d + lambda'M d / l0) for AT2 (eq. implicit_gc_l0_element_term)
- * and its AT1 counterpart; nodes held at d_prev pass their adjoint to d_prev.
+ * and its AT1 counterpart; nodes held at d_prev pass their adjoint to d_prev,
+ * nodes held at 1 pass none.  The adjoint CG warm-starts from the previous
+ * call's multiplier held by the handle.  Projected bounds only.
  * adj_np1 is read only; adj_n must not alias adj_np1, s_n or s_np1.
  */
 pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt,
@@ -242,8 +250,8 @@ const char* pf_version(void);
  * Kernel timing: when enabled, every kernel launch of this handle is
  * bracketed by HIP events on its stream.  pf_timer_read synchronises the
  * stream, returns the summed milliseconds and launch count of one kernel
- * family (0 explicit step, 1 damage matvec, 2 damage update, 3 adjoint)
- * and resets that family.
+ * family (0 explicit step, 1 damage matvec, 2 damage update, 3 adjoint
+ * kernels, 4 per-instance CG reductions) and resets that family.
  */
 pf_status_t pf_timer_enable(pf_mesh_t m, int32_t on);
 pf_status_t pf_timer_read(pf_mesh_t m, int32_t family, double* total_ms, int64_t* launches);

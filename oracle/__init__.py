@@ -14,10 +14,10 @@ triangle mesh:
   star-convex variant), degradation g(d) and stress (Sec. 2.1-2.2),
 * element forces scattered into the internal force, velocity-Verlet
   predictor/corrector (eq. vv_u, vv_a, vv_v) and the history maximum,
-* the damage update as the exact minimiser of the bound-constrained
-  quadratic programme of the AT1/AT2 weak form (eq. damage_pde_at2,
-  eq. damage_pde_at1, consistent mass of Sec. 2.4), solved by a
-  primal-dual active-set method with sparse LU,
+* the damage update as the exact minimiser of the quadratic programme of
+  the AT1/AT2 weak form (eq. damage_pde_at2, eq. damage_pde_at1,
+  consistent mass of Sec. 2.4) over d_n <= d <= 1, solved by a primal-dual
+  active-set method with sparse LU,
 * energies and, by forward-mode differentiation of the whole trajectory, the
   derivative of the final-damage loss (eq. inversion_loss) with respect to
   G_c, using the implicit rule of Sec. 4.2 for the damage solve.
@@ -27,11 +27,11 @@ Every function is FP64.  Pinned by the ``-m "not gpu"`` tests in
 """
 from .constitutive import elastic_constants, split_energy
 from .fem import (Mesh, cfl_dt, element_strain, internal_force, lumped_mass, make_mesh)
-from .damage import (DamageQP, assemble_damage, energies, kkt_residuals, solve_bound_qp,
+from .damage import (DamageQP, assemble_damage, energies, kkt_residuals, solve_bound_qp, solve_box_qp,
                      stiffness_matrix, mass_matrix)
 from .step import Material, State, explicit_step, initial_state, run, staggered_step, loss_and_grad
 
 __all__ = ["elastic_constants", "split_energy", "Mesh", "cfl_dt", "element_strain", "internal_force",
            "lumped_mass", "make_mesh", "DamageQP", "assemble_damage", "energies", "kkt_residuals",
-           "solve_bound_qp", "stiffness_matrix", "mass_matrix", "Material", "State", "explicit_step",
+           "solve_bound_qp", "solve_box_qp", "stiffness_matrix", "mass_matrix", "Material", "State", "explicit_step",
            "initial_state", "run", "staggered_step", "loss_and_grad"]

@@ -12,9 +12,11 @@ A d = b with
 with K^e_kl = A_e grad phi_k . grad phi_l and the consistent element mass
 M^e_kl = A_e (1 + delta_kl) / 12 of Sec. 2.4.  Irreversibility and the lower
 bound make the update the minimiser of 1/2 d'Ad - b'd over d >= lb with
-lb = d_n (Sec. 2.4, bound enforcement); the upper bound d <= 1 is applied
-afterwards by min(d, 1).  The paper's AT2 alternative (unconstrained solve,
-then clamp to [d_n, 1]) is the 'postclamp' mode.
+lb = d_n (Sec. 2.4, bound enforcement); the upper bound d <= 1 is imposed
+as a second bound of the same programme, so the update is the minimiser over
+d_n <= d <= 1 (the phase field lives in [0, 1], Sec. 2.1).  The paper's AT2
+alternative (unconstrained solve, then clamp to [d_n, 1]) is the 'postclamp'
+mode.
 
 The exact minimiser is found by a primal-dual active-set iteration with a
 sparse LU solve on the free set; the result is verified against the KKT
@@ -91,71 +93,88 @@ def assemble_damage(mesh: Mesh, H: np.ndarray, Gc: float, l0: float, model: int,
     return A, b
 
 
-def kkt_residuals(A, b, lb, x):
-    """Scaled KKT violations of min 1/2 x'Ax - b'x, x >= lb.
+def kkt_residuals(A, b, lb, x, ub=None):
+    """Scaled KKT violations of min 1/2 x'Ax - b'x over lb <= x <= ub.
 
     Returns (bound violation, max |r_i|/A_ii over free nodes, max r_i/A_ii over
-    nodes at the bound) with r = b - A x.  All three are <= 0 or small at the
-    minimiser.
+    nodes at the lower bound, max -r_i/A_ii over nodes at the upper bound)
+    with r = b - A x; nodes with lb_i = ub_i are fixed and carry no sign
+    condition.  All are <= 0 or small at the minimiser.
     """
     r = b - A @ x
     dg = A.diagonal()
-    at = x <= lb
-    free = ~at
-    viol = float(np.max(lb - x)) if len(x) else 0.0
+    ub = np.full(len(x), np.inf) if ub is None else np.asarray(ub, dtype=np.float64)
+    fixed = np.asarray(lb) >= ub          # lb = ub: the node is fixed, its multiplier has either sign
+    lo = (x <= lb) & ~fixed
+    up = (x >= ub) & ~lo & ~fixed
+    free = ~(lo | up | fixed)
+    viol = float(max(np.max(lb - x), np.max(x - ub))) if len(x) else 0.0
     rf = float(np.max(np.abs(r[free]) / dg[free])) if free.any() else 0.0
-    ra = float(np.max(r[at] / dg[at])) if at.any() else -np.inf
-    return viol, rf, ra
+    ra = float(np.max(r[lo] / dg[lo])) if lo.any() else -np.inf
+    ru = float(np.max(-r[up] / dg[up])) if up.any() else -np.inf
+    return viol, rf, ra, ru
+
+
+def solve_box_qp(A, b, lb, ub=None, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9,
+                 kkt_tol: float = 1e-13):
+    """Exact minimiser of 1/2 x'Ax - b'x subject to lb <= x <= ub (ub = None: no upper bound).
+
+    Primal-dual active set on the gradient g = A x - b: a node is held at its
+    lower bound when g_i + A_ii (lb_i - x_i) > 0 and at its upper bound when
+    g_i + A_ii (ub_i - x_i) < 0; free nodes solve A_FF x_F = b_F - A_FH x_H
+    exactly (sparse LU).  The iteration stops as soon as the iterate satisfies
+    the KKT conditions to rounding (free nodes inside the bounds to kkt_tol,
+    scaled multipliers of held nodes of the right sign to kkt_tol), or when
+    the sets repeat.  Nodes at a degenerate free boundary (x_i at a bound with
+    zero multiplier, e.g. the edge of the AT1 support) would otherwise flip
+    between the sets on rounding noise.  Returns (x, lower mask, upper mask).
+    """
+    A = sp.csr_matrix(A)
+    lb = np.asarray(lb, dtype=np.float64)
+    ub = np.full(len(b), np.inf) if ub is None else np.asarray(ub, dtype=np.float64)
+    dg = A.diagonal()
+    x = np.clip(lb if x0 is None else np.asarray(x0, dtype=np.float64), lb, ub)
+    g = A @ x - b
+    lo = (g + dg * (lb - x)) > 0
+    up = ((g + dg * (ub - x)) < 0) & ~lo
+    seen = set()
+    for _ in range(max_iter):
+        key = lo.tobytes() + up.tobytes()
+        if key in seen:
+            raise RuntimeError("active-set iteration cycled")
+        seen.add(key)
+        held = lo | up
+        free = ~held
+        x = np.where(lo, lb, np.where(up, ub, 0.0))
+        if free.any():
+            Aff = A[free][:, free].tocsc()
+            rhs = b[free] - A[free][:, held] @ x[held]
+            x[free] = spla.spsolve(Aff, rhs) if free.sum() > 1 else rhs / Aff.toarray()[0, 0]
+        g = A @ x - b
+        g[free] = 0.0
+        if (np.all(x[free] >= lb[free] - kkt_tol) and np.all(x[free] <= ub[free] + kkt_tol)
+                and np.all(g[lo] / dg[lo] >= -kkt_tol) and np.all(g[up] / dg[up] <= kkt_tol)):
+            break
+        new_lo = (g + dg * (lb - x)) > 0
+        new_up = ((g + dg * (ub - x)) < 0) & ~new_lo
+        if np.array_equal(new_lo, lo) and np.array_equal(new_up, up):
+            break
+        lo, up = new_lo, new_up
+    else:
+        raise RuntimeError("active-set iteration did not converge")
+    x = np.clip(x, lb, ub)
+    if check:
+        viol, rf, ra, ru = kkt_residuals(A, b, lb, x, ub)
+        if viol > 0 or rf > tol or ra > tol or ru > tol:
+            raise RuntimeError(f"KKT check failed: viol={viol} rf={rf} ra={ra} ru={ru}")
+    return x, lo, up
 
 
 def solve_bound_qp(A, b, lb, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9,
                    kkt_tol: float = 1e-13):
-    """Exact minimiser of 1/2 x'Ax - b'x subject to x >= lb.
-
-    Primal-dual active set: with the multiplier mu = A x - b, a node is
-    active when mu_i - A_ii (x_i - lb_i) > 0; free nodes solve
-    A_FF x_F = b_F - A_FA lb_A exactly.  The iteration stops as soon as the
-    iterate satisfies the KKT conditions to rounding (free nodes not below
-    their bound by more than kkt_tol, scaled multipliers mu_i/A_ii of active
-    nodes not below -kkt_tol), or when the active set repeats.  Nodes at a
-    degenerate free boundary (x_i = lb_i and mu_i = 0, e.g. the edge of the
-    AT1 support) would otherwise flip between the two sets on rounding noise.
-    Returns (x, active mask) with x >= lb.
-    """
-    A = sp.csr_matrix(A)
-    lb = np.asarray(lb, dtype=np.float64)
-    dg = A.diagonal()
-    x = np.maximum(lb if x0 is None else np.asarray(x0, dtype=np.float64), lb)
-    mu = A @ x - b
-    act = (mu - dg * (x - lb)) > 0
-    seen = set()
-    for _ in range(max_iter):
-        key = act.tobytes()
-        if key in seen:
-            raise RuntimeError("active-set iteration cycled")
-        seen.add(key)
-        free = ~act
-        x = lb.copy()
-        if free.any():
-            Aff = A[free][:, free].tocsc()
-            rhs = b[free] - A[free][:, act] @ lb[act]
-            x[free] = spla.spsolve(Aff, rhs) if free.sum() > 1 else rhs / Aff.toarray()[0, 0]
-        mu = A @ x - b
-        mu[free] = 0.0
-        if np.all(x[free] >= lb[free] - kkt_tol) and np.all(mu[act] / dg[act] >= -kkt_tol):
-            break
-        new_act = (mu - dg * (x - lb)) > 0
-        if np.array_equal(new_act, act):
-            break
-        act = new_act
-    else:
-        raise RuntimeError("active-set iteration did not converge")
-    x = np.maximum(x, lb)
-    if check:
-        viol, rf, ra = kkt_residuals(A, b, lb, x)
-        if viol > 0 or rf > tol or ra > tol:
-            raise RuntimeError(f"KKT check failed: viol={viol} rf={rf} ra={ra}")
-    return x, act
+    """Exact minimiser of 1/2 x'Ax - b'x subject to x >= lb; returns (x, active mask)."""
+    x, lo, _ = solve_box_qp(A, b, lb, None, x0=x0, max_iter=max_iter, check=check, tol=tol, kkt_tol=kkt_tol)
+    return x, lo
 
 
 @dataclass
@@ -175,31 +194,32 @@ class DamageQP:
         return assemble_damage(self.mesh, H, Gc, self.l0, self.model, K=self.K)
 
     def solve(self, H, Gc, d_prev):
-        """Return (d_new, active, upper, x, A).
+        """Return (d_new, lower, upper, x, A).
 
-        x is the QP minimiser before min(., 1) (projected mode) or the
-        unconstrained solution (post-clamp mode); active marks nodes held at
-        d_prev, upper marks nodes cut by min(., 1).
+        Projected mode: d_new = x is the minimiser over d_prev <= d <= 1;
+        lower / upper mark nodes held at d_prev / at 1.  Post-clamp mode: x is
+        the unconstrained solution and d_new = min(max(x, d_prev), 1).
         """
         A, b = self.system(H, Gc)
         if self.bounds == "projected":
-            x, act = solve_bound_qp(A, b, d_prev, x0=d_prev)
-            upper = x > 1.0
-            return np.minimum(x, 1.0), act, upper, x, A
+            x, lo, up = solve_box_qp(A, b, d_prev, np.ones(len(b)), x0=d_prev)
+            return x, lo, up, x, A
         if self.bounds == "postclamp":
             x = spla.spsolve(A.tocsc(), b)
-            act = x < d_prev
-            xc = np.where(act, d_prev, x)
-            upper = xc > 1.0
-            return np.minimum(xc, 1.0), act, upper, x, A
+            lo = x < d_prev
+            xc = np.where(lo, d_prev, x)
+            up = xc > 1.0
+            return np.minimum(xc, 1.0), lo, up, x, A
         raise ValueError(self.bounds)
 
     def tangent(self, A, x, act, upper, H, Gc, dH, dGc, dlb):
         """Directional derivative of the update (implicit rule, Sec. 4.2).
 
-        Free nodes F solve A_FF xdot_F = (bdot - Adot x - A_FA lbdot_A)_F with
-        the active nodes following their bound; nodes cut by min(., 1) get 0.
-        In post-clamp mode the linear solve is unconstrained: A xdot = bdot - Adot x.
+        Projected mode: nodes held at d_prev follow it, nodes held at 1 do not
+        move, and the free nodes F solve
+        A_FF xdot_F = (bdot - Adot x - A_F,held xdot_held)_F.
+        Post-clamp mode: the linear solve is unconstrained, A xdot = bdot - Adot x,
+        and the clamp passes d_prev's tangent where x < d_prev and 0 where x > 1.
         """
         kappa_dg = {2: self.l0, 1: 0.75 * self.l0}[self.model]
         b0_dg = {2: 0.0, 1: -3.0 / (8.0 * self.l0)}[self.model]
@@ -208,15 +228,16 @@ class DamageQP:
         bdot = np.zeros(self.mesh.n_nodes)
         np.add.at(bdot, self.mesh.tri.numpy().ravel(),
                   np.repeat((2.0 * dH + dGc * b0_dg) * self.mesh.area.numpy() / 3.0, 3))
-        free = ~act
-        xdot = np.where(act, dlb, 0.0)
         if self.bounds == "projected":
+            held = act | upper
+            free = ~held
+            xdot = np.where(act, dlb, 0.0)
             if free.any():
                 rhs = (bdot - Adot_x - A @ xdot)[free]
                 xdot[free] = spla.spsolve(A[free][:, free].tocsc(), rhs)
-        else:
-            full = spla.spsolve(A.tocsc(), bdot - Adot_x)
-            xdot = np.where(act, dlb, full)
+            return xdot
+        full = spla.spsolve(A.tocsc(), bdot - Adot_x)
+        xdot = np.where(act, dlb, full)
         return np.where(upper, 0.0, xdot)
 
 

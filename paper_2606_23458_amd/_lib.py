@@ -82,7 +82,7 @@ PROTOTYPES = {
     "pf_explicit_step": [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(StatePtrs),
                          C.POINTER(StatePtrs), C.c_void_p, C.c_void_p],
     "pf_damage_solve": [C.c_void_p, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                        C.POINTER(CgOpts), C.c_void_p, C.c_void_p],
+                        C.c_void_p, C.POINTER(CgOpts), C.c_void_p, C.c_void_p],
     "pf_step_backward": [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(StatePtrs),
                          C.POINTER(StatePtrs), C.c_void_p, C.POINTER(StatePtrs), C.POINTER(StatePtrs),
                          C.c_void_p, C.POINTER(CgOpts), C.c_void_p, C.c_void_p],

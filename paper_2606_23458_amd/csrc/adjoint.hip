@@ -10,6 +10,7 @@
 //   d_prev  :  nodes held at the bound get dbar_i - (A lambda)_i.
 // Explicit step: hand-written reverse mode of the corrector, the node gather,
 // the element forces, the split stress (split_vjp), g(d) and the predictor.
+// Nodes held at 1 are fixed in the adjoint solve and pass no adjoint.
 // The history maximum passes its adjoint to psi+ where psi+ > H_n, else to H_n.
 #include "device_common.hpp"
 #include "split.hpp"
@@ -25,26 +26,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* 
   for (int i = threadIdx.x; i < t.n_own; i += kBlock) {
     const int g = t.node_begin + i;
     const uint8_t a = act[g];
-    const bool held = (a & PF_ACTIVE_LOWER) != 0;
-    const bool upper = (a & PF_ACTIVE_UPPER) != 0;
-    W[g] = held ? 1 : 0;
-    b[g] = (held || upper) ? T(0) : dbar[g];
-    if (held) lam[g] = T(0);
+    // nodes held at d_prev (1) or at 1 (2) are fixed in the adjoint solve
+    const uint8_t w = (a & PF_ACTIVE_LOWER) ? 1 : ((a & PF_ACTIVE_UPPER) ? 2 : 0);
+    W[g] = w;
+    b[g] = w ? T(0) : dbar[g];
+    if (w) lam[g] = T(0);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T>* __restrict__ ip, Ctl* ctl,
-                                                       double* part, const T* __restrict__ lam,
+__global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T>* __restrict__ ip, double* part, const T* __restrict__ lam,
                                                        const T* __restrict__ dnp1, const T* __restrict__ Hnp1,
                                                        const T* __restrict__ dbar, const T* __restrict__ hbar_in,
-                                                       const uint8_t* __restrict__ W, T* hbar, T* dprev_bar,
-                                                       double* dGc) {
+                                                       const uint8_t* __restrict__ W, T* hbar, T* dprev_bar) {
   __shared__ double red[kWaves];
-  __shared__ int sflag;
   const TileRec t = dm.tiles[blockIdx.x];
   const InstP<T> P = ip[t.inst];
-  Ctl* c = ctl + t.inst;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
   T* sl = reinterpret_cast<T*>(smem);
@@ -95,18 +92,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
     const int g = t.node_begin + i;
     T qi = T(0);
     for (int j = dm.lrow[g]; j < dm.lrow[g + 1]; ++j) qi += qc[dm.lcorner[j]];
-    dprev_bar[g] = W[g] ? dbar[g] - qi : T(0);
+    dprev_bar[g] = (W[g] == 1) ? dbar[g] - qi : T(0);
   }
   gsum = block_sum(gsum, red);
   if (tid == 0) part[8 * blockIdx.x + 7] = gsum;
-  if (!arrive_last(&c->cnt_c, c->ntiles, &sflag)) return;
+}
+
+// One workgroup per instance: dGc += the instance's tile partials, fixed order.
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(const Ctl* ctl, const double* part, double* dGc) {
+  __shared__ double red[kWaves];
+  const Ctl* c = ctl + blockIdx.x;
   double s = 0.0;
-  for (int k = tid; k < c->ntiles; k += kBlock) s += part[8 * (c->tile0 + k) + 7];
+  for (int k = threadIdx.x; k < c->ntiles; k += kBlock) s += part[8 * (c->tile0 + k) + 7];
   s = block_sum(s, red);
-  if (tid == 0) {
-    dGc[t.inst] += s;
-    c->cnt_c = 0;
-  }
+  if (threadIdx.x == 0) dGc[blockIdx.x] += s;
 }
 
 template <typename T, int S>
@@ -212,7 +211,7 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
                      static_cast<T*>(m->dw.b), m->dw.wset, lam);
   timer_end(m, 3, s);
   PF_HIP(hipGetLastError());
-  pf_status_t st = damage_cg(m, CG_LINEAR, s_np1->H, lam, lam, nullptr, o, stats, s);
+  pf_status_t st = damage_cg(m, CG_LINEAR, s_np1->H, lam, lam, nullptr, nullptr, o, stats, s);
   if (st != PF_OK) return st;
   int32_t max_loc = 0, max_te = 0;
   for (const TileRec& tr : m->tiles_h) {
@@ -222,10 +221,11 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   const size_t lds_d = (2 * size_t(max_loc) + 3 * size_t(max_te)) * sizeof(T) + 64;
   const size_t lds_e = (5 * size_t(max_loc) + 9 * size_t(max_te)) * sizeof(T) + 64;
   timer_begin(m, 3, s);
-  hipLaunchKernelGGL(k_adj_damage<T>, grid, block, lds_d, s, m->dm, ip, m->dw.ctl, m->dw.part, lam,
+  hipLaunchKernelGGL(k_adj_damage<T>, grid, block, lds_d, s, m->dm, ip, m->dw.part, lam,
                      static_cast<const T*>(s_np1->d), static_cast<const T*>(s_np1->H),
                      static_cast<const T*>(adj1->d), static_cast<const T*>(adj1->H), m->dw.wset,
-                     static_cast<T*>(m->dw.hbar), static_cast<T*>(adj0->d), dGc);
+                     static_cast<T*>(m->dw.hbar), static_cast<T*>(adj0->d));
+  hipLaunchKernelGGL(k_adj_reduce, dim3(m->n_inst), block, 0, s, m->dw.ctl, m->dw.part, dGc);
   const StateIn<T> sn = state_in<T>(s_n), sn1 = state_in<T>(s_np1), a1 = state_in<T>(adj1);
   const StateOut<T> a0 = state_out<T>(adj0);
   const T* hb = static_cast<const T*>(m->dw.hbar);

@@ -1,6 +1,6 @@
-// Device helpers shared by the kernels: state pointer bundles, deterministic
-// block reductions (wave64 butterflies, then a fixed-order combine of the
-// four waves) and the "last block of an instance" arrival test.
+// Device helpers shared by the kernels: state pointer bundles and
+// deterministic block reductions (wave64 butterflies, then a fixed-order
+// combine of the four waves).
 #pragma once
 
 #include "pf_internal.hpp"
@@ -87,22 +87,6 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 #pragma unroll
   for (int k = 1; k < kWaves; ++k) s = fmin(s, sh[k]);
   return s;
-}
-
-// Publish this block's partials (already stored by thread 0) and report
-// whether it is the last block of its instance to arrive.  Uses one integer
-// atomic per block; the caller resets the counter in the last block.
-__device__ __forceinline__ bool arrive_last(uint32_t* counter, int ntiles, int* sflag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(counter, 1u);
-    *sflag = (prev == uint32_t(ntiles - 1)) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *sflag != 0;
-  if (last) __threadfence();
-  return last;
 }
 
 }  // namespace pf

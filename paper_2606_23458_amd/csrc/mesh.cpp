@@ -151,8 +151,11 @@ pf_status_t upload_params(pf_mesh_s* m, const pf_params_t* p, const double* dt, 
   if (buf != m->instp_host) {
     // Parameters change rarely (a new Gc or dt); a blocking copy keeps the
     // host buffer's lifetime trivial.
+    std::vector<int> bnd(m->n_inst);
+    for (int k = 0; k < m->n_inst; ++k) bnd[k] = p[k].bounds;
     PF_HIP(hipStreamSynchronize(s));
     PF_HIP(hipMemcpy(m->dw.instp, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    PF_HIP(hipMemcpy(m->dw.bounds, bnd.data(), sizeof(int) * bnd.size(), hipMemcpyHostToDevice));
     m->instp_host.swap(buf);
   }
   return PF_OK;
@@ -572,6 +575,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   m->dw.ctl = static_cast<Ctl*>(tmpp);
   const size_t psz = (dtype == PF_F64) ? sizeof(InstP<double>) : sizeof(InstP<float>);
   if ((st = dev_alloc(m, size_t(n_instances) * psz, &m->dw.instp)) != PF_OK) { free_all(m); delete m; return st; }
+  if ((st = dev_alloc(m, size_t(n_instances) * sizeof(int), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
+  m->dw.bounds = static_cast<int*>(tmpp);
   {
     hipError_t e = hipHostMalloc((void**)&m->ctl_pinned, sizeof(Ctl) * n_instances, hipHostMallocDefault);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipHostMalloc"); }
@@ -678,7 +683,7 @@ extern "C" pf_status_t pf_timer_enable(pf_mesh_t m, int32_t on) {
 
 extern "C" pf_status_t pf_timer_read(pf_mesh_t m, int32_t family, double* total_ms, int64_t* launches) {
   if (!m || !total_ms || !launches) return fail(PF_ERR_ARG, "NULL argument");
-  if (family < 0 || family > 3) return fail(PF_ERR_ARG, "family must be 0..3");
+  if (family < 0 || family > 4) return fail(PF_ERR_ARG, "family must be 0..4");
   Timer& t = m->timers[family];
   if (t.used) {
     PF_HIP(hipEventSynchronize(t.ev[2 * t.used - 1]));

@@ -58,14 +58,15 @@ struct Ctl {
   int32_t pbuf;       // which search-direction buffer holds the current p
   int32_t ntiles;     // tiles of this instance
   int32_t tile0;      // first tile of this instance
-  int32_t pad0;
-  uint32_t cnt_a, cnt_b, cnt_c, pad1;   // arrival counters of the last-block reductions
+  int32_t flavor;     // 0 active-set updates between CG runs, 1 monotone projected CG (fallback)
+  uint32_t cnt_a, cnt_b, cnt_c;   // arrival counters of the last-block reductions
+  int32_t outer;      // active-set updates so far
   double rz, alpha, beta, amax, resid, pq;
   double ref;         // scale of the stopping test (1 for the damage QP, max |b_i|/A_ii for linear solves)
   double pad2;
 };
 
-enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2 };
+enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2, MODE_CHECK = 3 };
 
 // Device view of a mesh handle.
 struct DevMesh {
@@ -93,6 +94,7 @@ struct DevWork {
   double* part;                      // [n_tiles][8] block partials
   Ctl* ctl;                          // [n_inst]
   void* instp;                       // [n_inst] InstP<T>
+  int* bounds;                       // [n_inst] pf_params_t.bounds of each instance
 };
 
 struct Timer {
@@ -121,7 +123,7 @@ struct pf_mesh_s {
   std::vector<double> dt_cache;      // dt of the last explicit step (the damage solve reuses it)
   pf::Ctl* ctl_pinned = nullptr;     // pinned host copy of the control blocks
   bool timing = false;
-  pf::Timer timers[4];
+  pf::Timer timers[5];
 };
 
 namespace pf {
@@ -153,8 +155,8 @@ pf_status_t check_params(const pf_mesh_s* m, const pf_params_t* p, const double*
 // (b, W and the starting x prepared by the caller in the workspaces; the
 // stopping test is relative to max |b_i|/A_ii).
 enum { CG_QP = 0, CG_LINEAR = 1 };
-pf_status_t damage_cg(pf_mesh_s* m, int kind, const void* H, const void* lb, void* x, uint8_t* active_out,
-                      const pf_cg_opts_t* o, pf_cg_stats_t* stats, hipStream_t s);
+pf_status_t damage_cg(pf_mesh_s* m, int kind, const void* H, const void* lb, void* x, const uint8_t* guess,
+                      uint8_t* active_out, const pf_cg_opts_t* o, pf_cg_stats_t* stats, hipStream_t s);
 pf_status_t check_state(const pf_state_t* s, bool need_d, bool need_H, const char* name);
 bool states_share(const pf_state_t* a, const pf_state_t* b);
 

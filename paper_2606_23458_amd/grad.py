@@ -1,0 +1,121 @@
+"""Reverse-mode dL/dGc through a trajectory, with time-step checkpointing.
+
+The forward pass stores the state every ``checkpoint_every`` steps.  The
+backward pass walks the segments in reverse: it recomputes a segment from its
+checkpoint (the kernels are deterministic, so the recomputed states are
+bitwise the forward ones), then calls pf_step_backward for every step of the
+segment in reverse.  Memory holds T/K checkpoints plus K+1 segment states
+instead of T states (the tape reduction the paper names as future work in
+its conclusions).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .sim import Simulator, State, _stream
+
+
+def backward_step(sim: Simulator, s_n: State, s_np1: State, active_np1: torch.Tensor, adj_np1: State,
+                  adj_n: State, dGc: torch.Tensor) -> None:
+    """Adjoint of one staggered step (pf_step_backward); dGc (float64, device) is accumulated."""
+    a, b, c, d = s_n.ptrs(), s_np1.ptrs(), adj_np1.ptrs(), adj_n.ptrs()
+    o = sim.cg_adj.opts()
+    L.call("pf_step_backward", sim.mesh.handle, sim.params, sim.dt, C.byref(a), C.byref(b),
+           active_np1.data_ptr(), C.byref(c), C.byref(d), dGc.data_ptr(), C.byref(o), sim.stats.data_ptr(),
+           _stream())
+
+
+class TrajectoryRunner:
+    """Forward and checkpointed reverse sweeps of a Simulator."""
+
+    def __init__(self, sim: Simulator, steps: int, checkpoint_every: int = 50):
+        if steps < 1 or checkpoint_every < 1:
+            raise ValueError("steps and checkpoint_every must be >= 1")
+        self.sim = sim
+        self.steps = steps
+        self.K = checkpoint_every
+        mesh = sim.mesh
+        self.seg_states = [State(mesh) for _ in range(self.K + 1)]
+        self.seg_active = [torch.zeros(mesh.n_nodes, dtype=torch.uint8, device=mesh.device)
+                           for _ in range(self.K + 1)]
+        self.adj = [State(mesh), State(mesh)]
+        self.checkpoints: list[State] = []
+
+    def forward(self) -> State:
+        """Run all steps from the simulator's initial state; keep checkpoints (state + held flags)."""
+        sim = self.sim
+        sim.reset()
+        self.checkpoints = [(sim.state.clone(), sim.active.clone())]
+        for n in range(self.steps):
+            sim.step()
+            if (n + 1) % self.K == 0 and n + 1 < self.steps:
+                self.checkpoints.append((sim.state.clone(), sim.active.clone()))
+        return sim.state
+
+    def backward(self, d_bar: torch.Tensor) -> torch.Tensor:
+        """Reverse sweep from the adjoint of the final damage; returns dL/dGc per instance (float64)."""
+        sim = self.sim
+        mesh = sim.mesh
+        dGc = torch.zeros(mesh.n_instances, dtype=torch.float64, device=mesh.device)
+        cur, nxt = self.adj
+        cur.zero_()
+        cur.nodes[6].copy_(d_bar)
+        n_seg = len(self.checkpoints)
+        for sgi in range(n_seg - 1, -1, -1):
+            k0 = sgi * self.K
+            k1 = min(k0 + self.K, self.steps)
+            states = self.seg_states
+            states[0].copy_(self.checkpoints[sgi][0])
+            self.seg_active[0].copy_(self.checkpoints[sgi][1])
+            for j in range(k1 - k0):
+                sim.step_into(states[j], states[j + 1], self.seg_active[j + 1], self.seg_active[j])
+            for j in range(k1 - k0 - 1, -1, -1):
+                backward_step(sim, states[j], states[j + 1], self.seg_active[j + 1], cur, nxt, dGc)
+                cur, nxt = nxt, cur
+        self.adj = [cur, nxt]
+        return dGc
+
+
+class DamageTrajectory(torch.autograd.Function):
+    """d_T(Gc): final damage (internal node order) of a checkpointed trajectory.
+
+    Gc is a float64 tensor with one entry per instance; backward returns
+    dL/dGc from the reverse sweep.
+    """
+
+    @staticmethod
+    def forward(ctx, Gc: torch.Tensor, runner: TrajectoryRunner):
+        runner.sim.set_Gc(Gc.detach().cpu().numpy())
+        out = runner.forward()
+        ctx.runner = runner
+        return out.d.clone()
+
+    @staticmethod
+    def backward(ctx, d_bar: torch.Tensor):
+        runner: TrajectoryRunner = ctx.runner
+        g = runner.backward(d_bar.to(runner.sim.mesh.dtype).contiguous())
+        return g.to(d_bar.device), None
+
+
+def instance_mse(mesh, d: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """Per-instance nodewise mean squared error (eq. inversion_loss), float64."""
+    out = []
+    diff = (d.double() - target.double()) ** 2
+    for inf in mesh.info:
+        out.append(diff[inf.node_offset:inf.node_offset + inf.n_nodes].mean())
+    return torch.stack(out)
+
+
+def loss_and_grad(sim: Simulator, Gc, target: torch.Tensor, steps: int, checkpoint_every: int = 50,
+                  runner: TrajectoryRunner | None = None):
+    """Per-instance loss and dL/dGc (both float64 numpy) for the given Gc values."""
+    runner = runner or TrajectoryRunner(sim, steps, checkpoint_every)
+    g = torch.tensor(np.atleast_1d(np.asarray(Gc, dtype=np.float64)), device=sim.mesh.device, requires_grad=True)
+    d = DamageTrajectory.apply(g, runner)
+    L_ = instance_mse(sim.mesh, d, target)
+    L_.sum().backward()
+    return L_.detach().cpu().numpy(), g.grad.detach().cpu().numpy()

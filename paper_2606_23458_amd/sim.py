@@ -190,7 +190,7 @@ class Simulator:
     """Staggered explicit phase-field simulation of one or more instances on one GPU."""
 
     def __init__(self, problems, dtype: str | None = None, tile_nodes: int = 0, cg: CgConfig | None = None,
-                 dt: list[float] | None = None, mesh: Mesh | None = None):
+                 dt: list[float] | None = None, mesh: Mesh | None = None, cg_adj: CgConfig | None = None):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
@@ -208,8 +208,11 @@ class Simulator:
             for k, v in enumerate(dt):
                 self.dt[k] = float(v)
         self.cg = cg or CgConfig(tol=default_tol(self.dtype_code))
+        # adjoint solves stop relative to their right-hand side
+        self.cg_adj = cg_adj or CgConfig(tol=default_tol(self.dtype_code))
         self.stats = torch.zeros(n * 6, dtype=torch.int32, device=self.mesh.device)   # pf_cg_stats_t[n]
-        self.active = torch.zeros(self.mesh.n_nodes, dtype=torch.uint8, device=self.mesh.device)
+        self.active = self.initial_active()
+        self._active_next = torch.zeros_like(self.active)
         self.state = self.initial_state()
         self._next = State(self.mesh)
         self.steps_done = 0
@@ -222,8 +225,14 @@ class Simulator:
         return State.from_user(self.mesh, [{"u": p.u0, "v": p.v0, "a": p.a0, "d": p.d0, "H": p.H0}
                                            for p in self.problems])
 
+    def initial_active(self) -> torch.Tensor:
+        """Held-set seed for the first solve: nodes whose initial damage is already 1 (the notch)."""
+        d0 = self.mesh.nodes_to_internal([p.d0 for p in self.problems])
+        return torch.tensor((d0 >= 1.0).astype(np.uint8), device=self.mesh.device)
+
     def reset(self) -> None:
         self.state = self.initial_state()
+        self.active = self.initial_active()
         self.steps_done = 0
 
     # --- the two halves of the staggered step --------------------------------
@@ -233,19 +242,22 @@ class Simulator:
                _ptr(f_ext), _stream())
 
     def damage(self, H: torch.Tensor, d_prev: torch.Tensor, d_out: torch.Tensor,
-               active: torch.Tensor | None = None) -> None:
+               active: torch.Tensor | None = None, guess: torch.Tensor | None = None) -> None:
+        """Damage update; `guess` seeds the held set (normally the previous step's flags)."""
         o = self.cg.opts()
         L.call("pf_damage_solve", self.mesh.handle, self.params, H.data_ptr(), d_prev.data_ptr(), d_out.data_ptr(),
-               _ptr(active), C.byref(o), self.stats.data_ptr(), _stream())
+               _ptr(guess), _ptr(active), C.byref(o), self.stats.data_ptr(), _stream())
 
-    def step_into(self, s_in: State, s_out: State, active: torch.Tensor | None = None) -> None:
+    def step_into(self, s_in: State, s_out: State, active_out: torch.Tensor, active_in: torch.Tensor | None) -> None:
+        """One staggered step s_in -> s_out; active_in are the flags of the solve that produced s_in.d."""
         self.explicit(s_in, s_out)
-        self.damage(s_out.H, s_in.d, s_out.d, active if active is not None else self.active)
+        self.damage(s_out.H, s_in.d, s_out.d, active_out, active_in)
 
     def step(self, n: int = 1) -> State:
         for _ in range(n):
-            self.step_into(self.state, self._next)
+            self.step_into(self.state, self._next, self._active_next, self.active)
             self.state, self._next = self._next, self.state
+            self.active, self._active_next = self._active_next, self.active
             self.steps_done += 1
         return self.state
 

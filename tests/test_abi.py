@@ -97,7 +97,7 @@ def test_argument_errors():
     assert st == L.PF_ERR_ARG and "tile_nodes" in msg
     assert lib.pf_mesh_create(None, 1, 0, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_explicit_step(None, None, None, None, None, None, None) == L.PF_ERR_ARG
-    assert lib.pf_damage_solve(None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG
+    assert lib.pf_damage_solve(None, None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_step_backward(None, None, None, None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_mesh_destroy(None) == L.PF_OK
     tot = L.Totals()

@@ -6,7 +6,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 import workloads as w
-from oracle.damage import DamageQP, assemble_damage, kkt_residuals, node_area, solve_bound_qp
+from oracle.damage import DamageQP, assemble_damage, kkt_residuals, node_area, solve_bound_qp, solve_box_qp
 from oracle.fem import make_mesh
 from tests._helpers import rel
 
@@ -91,8 +91,66 @@ def test_qp_unique_kkt_point_by_enumeration(seed):
     assert all(np.allclose(s, ref, atol=1e-12, rtol=0) for s in sols)
     x, _ = solve_bound_qp(A, b, lb)
     assert np.max(np.abs(x - ref)) < 1e-12
-    viol, rf, ra = kkt_residuals(A, b, lb, x)
+    viol, rf, ra, ru = kkt_residuals(A, b, lb, x)
     assert viol <= 0 and rf < 1e-12 and ra < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_box_qp_unique_kkt_point_by_enumeration(seed):
+    """P8 (c): with d <= 1 as well, enumerate all 3^9 (free / lower / upper) sets on a 9-node mesh."""
+    m, mesh = mesh_of(2, 2, 2.5e-4, 0.2, seed, random_diag=True)
+    n = mesh.n_nodes
+    r = np.random.default_rng(10 + seed)
+    H = r.uniform(0, 40000, mesh.n_elems)
+    lb = np.where(r.random(n) < 0.5, r.uniform(0.3, 1.0, n), 0.0)
+    ub = np.ones(n)
+    A, b = assemble_damage(mesh, H, GC, L0, 2)
+    Ad = A.toarray()
+    sols = []
+    for mask in itertools.product([0, 1, 2], repeat=n):
+        st = np.array(mask)
+        lo, up = st == 1, st == 2
+        free = st == 0
+        x = np.where(lo, lb, np.where(up, ub, 0.0))
+        if free.any():
+            held = ~free
+            x[free] = np.linalg.solve(Ad[np.ix_(free, free)], b[free] - Ad[np.ix_(free, held)] @ x[held])
+        g = Ad @ x - b
+        eps = 1e-13 * np.abs(Ad).max()
+        if (np.all(x[free] >= lb[free] - 1e-13) and np.all(x[free] <= 1 + 1e-13)
+                and np.all(g[lo] >= -eps) and np.all(g[up] <= eps) and np.all(lb <= ub)):
+            sols.append(x)
+    assert len(sols) >= 1
+    assert all(np.allclose(s, sols[0], atol=1e-12, rtol=0) for s in sols)
+    x, lo, up = solve_box_qp(A, b, lb, ub)
+    assert np.max(np.abs(x - sols[0])) < 1e-12
+    viol, rf, ra, ru = kkt_residuals(A, b, lb, x, ub)
+    assert viol <= 0 and rf < 1e-12 and ra < 1e-12 and ru < 1e-12
+
+
+def test_upper_bound_is_a_constraint_of_the_programme():
+    """The update over [d_prev, 1] differs from clamping the lower-bounded minimiser."""
+    from oracle.step import Sim, initial_state
+    p = w.small_plate(32, 16, seed=3)
+    sim = Sim(p)
+    st = initial_state(p)
+    found = False
+    for _ in range(120):
+        u1, v1, a1, H1, _ = sim.explicit(st)
+        A, b = sim.qp.system(H1.numpy(), p.Gc)
+        lb = st.d.numpy()
+        x1, _ = solve_bound_qp(A, b, lb, x0=lb)
+        if x1.max() > 1.0:
+            xb, lo, up = solve_box_qp(A, b, lb, np.ones_like(lb), x0=lb)
+            assert up.any() and np.all(xb <= 1.0) and np.all(xb >= lb)
+            viol, rf, ra, ru = kkt_residuals(A, b, lb, xb, np.ones_like(lb))
+            assert viol <= 0 and rf < 1e-12 and ra < 1e-12 and ru < 1e-12
+            # clamping the lower-bounded minimiser is not the box minimiser
+            assert np.max(np.abs(np.minimum(x1, 1.0) - xb)) > 1e-8
+            found = True
+            break
+        st = sim.step(st)
+    assert found
 
 
 def crack_row_problem(ny_cells, ratio, model, nx=None):
@@ -181,8 +239,8 @@ def test_postclamp_mode():
     # the projected minimiser differs and satisfies the KKT conditions
     qpp = DamageQP(mesh, L0, 2)
     dp, actp, _, xp, _ = qpp.solve(H, GC, lb)
-    viol, rf, ra = kkt_residuals(A2, b2, lb, xp)
-    assert viol <= 0 and rf < 1e-11 and ra < 1e-11
+    viol, rf, ra, ru = kkt_residuals(A2, b2, lb, xp, np.ones_like(lb))
+    assert viol <= 0 and rf < 1e-11 and ra < 1e-11 and ru < 1e-11
 
 
 def test_qp_tangent_by_finite_differences():
@@ -218,6 +276,6 @@ def test_at1_degenerate_free_boundary_early_steps():
         u1, v1, a1, H1, _ = sim.explicit(st)
         A, b = sim.qp.system(H1.numpy(), p.Gc)
         x, act = solve_bound_qp(A, b, st.d.numpy(), x0=st.d.numpy())
-        viol, rf, ra = kkt_residuals(A, b, st.d.numpy(), x)
+        viol, rf, ra, ru = kkt_residuals(A, b, st.d.numpy(), x)
         assert viol <= 0 and rf < 1e-12 and ra < 1e-12
         st = sim.step(st)
