@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--tile-nodes", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also copy a 256 MiB device buffer 3 times (known traffic, for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -208,6 +210,13 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.copy_calib:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     res = run_headline(args.steps, args.warmup, args.tile_nodes)
     ms_step = res["ms"] / args.steps
     value = res["ne"] * args.steps / (res["ms"] / 1e3)

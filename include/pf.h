@@ -116,6 +116,16 @@ typedef struct {
                                 rounds to stop early (the default path);
                                 0: enqueue exactly max_iter rounds and never
                                 synchronise (suitable for HIP-graph capture) */
+    int32_t start;           /* damage solve only.  0: start from d_prev;
+                                1: start from clamp(2 d_prev - d, d_prev, 1),
+                                where the output array d holds, on entry, the
+                                damage of the step before d_prev (a linear
+                                extrapolation in time) */
+    int32_t monotone;        /* damage solve only.  1: use the monotone
+                                projected CG from the start instead of
+                                held-set updates between CG runs (slower; the
+                                solver falls back to it by itself when the
+                                held set does not settle) */
 } pf_cg_opts_t;
 
 /* Per-instance solve statistics, written to DEVICE memory by the solve. */

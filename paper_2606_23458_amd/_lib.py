@@ -42,7 +42,8 @@ class StatePtrs(C.Structure):
 
 
 class CgOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32), ("start", C.c_int32),
+                ("monotone", C.c_int32)]
 
 
 class CgStats(C.Structure):

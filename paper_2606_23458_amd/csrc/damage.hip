@@ -20,7 +20,10 @@
 // cut at the first bound and followed by a projected Jacobi-gradient step of
 // length 0.25 (below 2/lambda_max(D^-1 A) for row sums of |A_ij|/A_ii up to
 // 8), and held nodes are released only when CG on the current face has
-// converged.  Nodes with d_prev = 1 are fixed.
+// converged.  Nodes with d_prev = 1 are fixed.  A CG run is also cut short
+// for a check when a quarter of its free nodes have left [d_prev, 1] (a far
+// wrong held set, e.g. the first AT1 step, would otherwise cost a solve of a
+// nearly singular free system).
 //
 // Each CG round is four launches: over the tile grid
 //   A  q = A s with s = x (restart, check) or s = p = z + beta p_old
@@ -51,15 +54,18 @@ struct DmgArgs {
   const T* __restrict__ H;
   const T* __restrict__ lb;
   const uint8_t* __restrict__ guess;
-  T* x;
+  T* x;                // the iterate (a workspace for the damage solve)
+  T* dout;             // damage solve: output array (read at set-up when start = 1)
+  T* mte;              // per-solve mass coefficient of each tile element
   T* b; T* dinv; T* r; T* z; T* p0; T* p1; T* q;
   uint8_t* W;
   double tol;
   int32_t max_iter;
   int32_t kind;        // CG_QP or CG_LINEAR
+  int32_t start;       // 1: extrapolated start for the damage solve
 };
 
-__global__ void k_dmg_init(Ctl* ctl, int n_inst, int kind) {
+__global__ void k_dmg_init(Ctl* ctl, int n_inst, int kind, int monotone) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_inst) return;
   Ctl& c = ctl[k];
@@ -72,11 +78,9 @@ __global__ void k_dmg_init(Ctl* ctl, int n_inst, int kind) {
   c.flags = 0;
   c.nact = 0;
   c.pbuf = 0;
-  c.flavor = 0;
+  c.flavor = (kind == CG_QP && monotone) ? 1 : 0;
   c.outer = 0;
-  c.cnt_a = 0;
-  c.cnt_b = 0;
-  c.cnt_c = 0;
+  c.inner = 0;
   c.rz = 0.0;
   c.alpha = 0.0;
   c.beta = 0.0;
@@ -84,6 +88,11 @@ __global__ void k_dmg_init(Ctl* ctl, int n_inst, int kind) {
   c.resid = 0.0;
   c.pq = 0.0;
   c.ref = (kind == CG_QP) ? 1.0 : 0.0;
+}
+
+template <typename T>
+__device__ __forceinline__ T clamp01(T v, T lo) {
+  return v < lo ? lo : (v > T(1) ? T(1) : v);
 }
 
 template <typename T>
@@ -116,8 +125,16 @@ __global__ __launch_bounds__(kBlock) void k_dmg_a(DmgArgs<T> a) {
     const int g = (i < t.n_own) ? t.node_begin + i : a.dm.halo_idx[t.halo_begin + (i - t.n_own)];
     T v;
     if (setup && qp) {
-      // start at d_prev, or at 1 where the guess holds the node at the upper bound
-      v = (projected && a.guess && (a.guess[g] & PF_ACTIVE_UPPER)) ? T(1) : a.lb[g];
+      // start at d_prev (or its extrapolation in time), or at 1 where the guess
+      // holds the node at the upper bound
+      const T lbv = a.lb[g];
+      if (projected && a.guess && (a.guess[g] & PF_ACTIVE_UPPER)) {
+        v = T(1);
+      } else if (a.start) {
+        v = clamp01<T>(T(2) * lbv - a.dout[g], lbv);
+      } else {
+        v = lbv;
+      }
       if (i < t.n_own) a.x[g] = v;
     } else if (matvec_x) {
       v = a.x[g];
@@ -137,9 +154,15 @@ __global__ __launch_bounds__(kBlock) void k_dmg_a(DmgArgs<T> a) {
     const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
     const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
     const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-    const T He = a.H[a.dm.te_gid[te]];
     const T kA = P.kap * A;
-    const T mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
+    T mA, He = T(0);
+    if (setup) {
+      He = a.H[a.dm.te_gid[te]];
+      mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
+      a.mte[te] = mA;
+    } else {
+      mA = a.mte[te];
+    }
     const T s0 = s[c0], s1 = s[c1], s2 = s[c2];
     const T gpx = g0x * s0 + g1x * s1 + g2x * s2;
     const T gpy = g0y * s0 + g1y * s1 + g2y * s2;
@@ -220,11 +243,6 @@ __global__ __launch_bounds__(kBlock) void k_dmg_reduce_a(Ctl* ctl, const double*
   c->alpha = alpha;
   c->hit = hit;
   c->pbuf ^= 1;
-}
-
-template <typename T>
-__device__ __forceinline__ T clamp01(T v, T lo) {
-  return v < lo ? lo : (v > T(1) ? T(1) : v);
 }
 
 template <typename T>
@@ -314,7 +332,12 @@ __global__ __launch_bounds__(kBlock) void k_dmg_b(DmgArgs<T> a) {
         continue;
       }
       T xn = xv + al * pv;
-      if (monotone) xn = clamp01<T>(xn, a.lb[g]);
+      if (monotone) {
+        xn = clamp01<T>(xn, a.lb[g]);
+      } else if (projected && !w) {
+        const double xd = double(xn);
+        if (double(a.lb[g]) - xd > tol || xd - 1.0 > tol) ch += 1.0;   // free node outside the bounds
+      }
       a.x[g] = xn;
       const T ri = a.r[g] - al * qv;
       const T zi = w ? T(0) : di * ri;
@@ -375,6 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg_reduce_b(Ctl* ctl, const double*
   const bool monotone = projected && (c->flavor != 0);
   const bool setup = c->setup != 0;
   c->iters += 1;
+  c->inner = (mode == MODE_ITER) ? c->inner + 1 : 0;
   if (setup && !qp) c->ref = srb;   // linear solves stop relative to max |b_i|/A_ii
   const double tl = tol * c->ref;
   const double rs = c->ref > 0.0 ? c->ref : 1.0;
@@ -431,8 +455,10 @@ __global__ __launch_bounds__(kBlock) void k_dmg_reduce_b(Ctl* ctl, const double*
     c->beta = srz / c->rz;
     c->rz = srz;
     c->resid = scf / rs;
-    if (scf <= tl || srz == 0.0) {
-      // this CG run converged on its recurrence residual
+    const bool early = projected && !monotone && c->inner >= 2 && sch > 0.25 * double(c->nnodes - c->nact);
+    if (scf <= tl || srz == 0.0 || early) {
+      // this CG run converged on its recurrence residual, or a quarter of the
+      // free nodes already left their bounds: update the held set now
       if (projected && !monotone) {
         c->mode = MODE_CHECK;
       } else {
@@ -478,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg_final(DmgArgs<T> a, uint8_t* act
           act |= PF_ACTIVE_UPPER;
         }
       }
-      a.x[g] = xv;
+      a.dout[g] = xv;
       if (active_out) active_out[g] = act;
     }
   }
@@ -495,9 +521,11 @@ __global__ __launch_bounds__(kBlock) void k_dmg_final(DmgArgs<T> a, uint8_t* act
 
 template <typename T>
 static DmgArgs<T> dmg_args(pf_mesh_s* m, int kind, const void* H, const void* d_prev, void* d,
-                           const uint8_t* guess, double tol, int max_iter) {
+                           const uint8_t* guess, double tol, int max_iter, int start) {
   DmgArgs<T> a;
   a.kind = kind;
+  a.start = (kind == CG_QP) ? start : 0;
+  a.mte = static_cast<T*>(m->dw.mte);
   a.dm = m->dm;
   a.ip = static_cast<const InstP<T>*>(m->dw.instp);
   a.ctl = m->dw.ctl;
@@ -505,7 +533,9 @@ static DmgArgs<T> dmg_args(pf_mesh_s* m, int kind, const void* H, const void* d_
   a.H = static_cast<const T*>(H);
   a.lb = static_cast<const T*>(d_prev);
   a.guess = guess;
-  a.x = static_cast<T*>(d);
+  // the damage solve iterates in a workspace and writes d at the end; linear solves iterate in place
+  a.x = (kind == CG_QP) ? static_cast<T*>(m->dw.xw) : static_cast<T*>(d);
+  a.dout = static_cast<T*>(d);
   a.b = static_cast<T*>(m->dw.b);
   a.dinv = static_cast<T*>(m->dw.dinv);
   a.r = static_cast<T*>(m->dw.r);
@@ -523,10 +553,10 @@ template <typename T>
 static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* d_prev, void* d,
                              const uint8_t* guess, uint8_t* active_out, const pf_cg_opts_t* o,
                              pf_cg_stats_t* stats, hipStream_t s) {
-  DmgArgs<T> a = dmg_args<T>(m, kind, H, d_prev, d, guess, o->tol, o->max_iter);
+  DmgArgs<T> a = dmg_args<T>(m, kind, H, d_prev, d, guess, o->tol, o->max_iter, o->start);
   const dim3 grid(m->n_tiles), block(kBlock), igrid(m->n_inst);
   const size_t lds = m->max_lds_damage;
-  hipLaunchKernelGGL(k_dmg_init, dim3((m->n_inst + 63) / 64), dim3(64), 0, s, m->dw.ctl, m->n_inst, kind);
+  hipLaunchKernelGGL(k_dmg_init, dim3((m->n_inst + 63) / 64), dim3(64), 0, s, m->dw.ctl, m->n_inst, kind, o->monotone);
   auto round = [&]() {
     timer_begin(m, 1, s);
     hipLaunchKernelGGL(k_dmg_a<T>, grid, block, lds, s, a);

@@ -567,6 +567,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     if ((st = dev_alloc(m, nb, v)) != PF_OK) { free_all(m); delete m; return st; }
   void* tmpp;
   if ((st = dev_alloc(m, size_t(m->n_elems) * w, &m->dw.hbar)) != PF_OK) { free_all(m); delete m; return st; }
+  if ((st = dev_alloc(m, size_t(m->n_nodes) * w, &m->dw.xw)) != PF_OK) { free_all(m); delete m; return st; }
+  if ((st = dev_alloc(m, size_t(m->n_te) * w, &m->dw.mte)) != PF_OK) { free_all(m); delete m; return st; }
   if ((st = dev_alloc(m, size_t(m->n_nodes), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
   m->dw.wset = static_cast<uint8_t*>(tmpp);
   if ((st = dev_alloc(m, size_t(m->n_tiles) * 8 * sizeof(double), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
@@ -588,6 +590,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     for (int k = 0; k < n_instances; ++k) {
       c[k].ntiles = m->info[k].n_tiles;
       c[k].tile0 = m->info[k].tile_offset;
+      c[k].nnodes = m->info[k].n_nodes;
       c[k].mode = MODE_DONE;
     }
     hipError_t e = hipMemcpy(m->dw.ctl, c.data(), sizeof(Ctl) * n_instances, hipMemcpyHostToDevice);

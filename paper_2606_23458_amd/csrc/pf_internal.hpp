@@ -59,7 +59,9 @@ struct Ctl {
   int32_t ntiles;     // tiles of this instance
   int32_t tile0;      // first tile of this instance
   int32_t flavor;     // 0 active-set updates between CG runs, 1 monotone projected CG (fallback)
-  uint32_t cnt_a, cnt_b, cnt_c;   // arrival counters of the last-block reductions
+  int32_t nnodes;     // nodes of this instance
+  int32_t inner;      // CG iterations since the last restart or check
+  int32_t pad1;
   int32_t outer;      // active-set updates so far
   double rz, alpha, beta, amax, resid, pq;
   double ref;         // scale of the stopping test (1 for the damage QP, max |b_i|/A_ii for linear solves)
@@ -91,6 +93,8 @@ struct DevWork {
   uint8_t* wset;
   void* lam; void* t0; void* t1;     // adjoint scratch vectors
   void* hbar;                        // [n_elems] adjoint of H_{n+1} (adjoint step scratch)
+  void* xw;                          // [n_nodes] damage iterate of the solve
+  void* mte;                         // [n_te] per-solve mass coefficient (c0 + cH H_e) A_e / 12 of each tile element
   double* part;                      // [n_tiles][8] block partials
   Ctl* ctl;                          // [n_inst]
   void* instp;                       // [n_inst] InstP<T>

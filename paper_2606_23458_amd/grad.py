@@ -49,11 +49,13 @@ class TrajectoryRunner:
         """Run all steps from the simulator's initial state; keep checkpoints (state + held flags)."""
         sim = self.sim
         sim.reset()
-        self.checkpoints = [(sim.state.clone(), sim.active.clone())]
+        # a checkpoint keeps the state, the held flags and the previous damage
+        # field (the damage solve extrapolates from it)
+        self.checkpoints = [(sim.state.clone(), sim.active.clone(), sim._next.d.clone())]
         for n in range(self.steps):
             sim.step()
             if (n + 1) % self.K == 0 and n + 1 < self.steps:
-                self.checkpoints.append((sim.state.clone(), sim.active.clone()))
+                self.checkpoints.append((sim.state.clone(), sim.active.clone(), sim._next.d.clone()))
         return sim.state
 
     def backward(self, d_bar: torch.Tensor) -> torch.Tensor:
@@ -69,9 +71,11 @@ class TrajectoryRunner:
             k0 = sgi * self.K
             k1 = min(k0 + self.K, self.steps)
             states = self.seg_states
-            states[0].copy_(self.checkpoints[sgi][0])
-            self.seg_active[0].copy_(self.checkpoints[sgi][1])
+            ck_state, ck_active, ck_dprev = self.checkpoints[sgi]
+            states[0].copy_(ck_state)
+            self.seg_active[0].copy_(ck_active)
             for j in range(k1 - k0):
+                states[j + 1].d.copy_(ck_dprev if j == 0 else states[j - 1].d)
                 sim.step_into(states[j], states[j + 1], self.seg_active[j + 1], self.seg_active[j])
             for j in range(k1 - k0 - 1, -1, -1):
                 backward_step(sim, states[j], states[j + 1], self.seg_active[j + 1], cur, nxt, dGc)

@@ -177,9 +177,11 @@ class CgConfig:
     tol: float = 1e-12
     max_iter: int = 2000
     check_every: int = 8
+    start: int = 1          # damage solve: 1 = extrapolate from the two previous damage fields
+    monotone: int = 0       # damage solve: 1 = monotone projected CG from the start
 
     def opts(self) -> L.CgOpts:
-        return L.CgOpts(self.tol, self.max_iter, self.check_every)
+        return L.CgOpts(self.tol, self.max_iter, self.check_every, self.start, self.monotone)
 
 
 def default_tol(dtype: str) -> float:
@@ -233,6 +235,7 @@ class Simulator:
     def reset(self) -> None:
         self.state = self.initial_state()
         self.active = self.initial_active()
+        self._next.zero_()
         self.steps_done = 0
 
     # --- the two halves of the staggered step --------------------------------
@@ -249,7 +252,11 @@ class Simulator:
                _ptr(guess), _ptr(active), C.byref(o), self.stats.data_ptr(), _stream())
 
     def step_into(self, s_in: State, s_out: State, active_out: torch.Tensor, active_in: torch.Tensor | None) -> None:
-        """One staggered step s_in -> s_out; active_in are the flags of the solve that produced s_in.d."""
+        """One staggered step s_in -> s_out; active_in are the flags of the solve that produced s_in.d.
+
+        With the extrapolated start (cg.start = 1), s_out.d must hold the damage
+        of the step before s_in on entry; the explicit step leaves it untouched.
+        """
         self.explicit(s_in, s_out)
         self.damage(s_out.H, s_in.d, s_out.d, active_out, active_in)
 

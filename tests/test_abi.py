@@ -36,7 +36,7 @@ def test_struct_layouts_match_header(tmp_path):
         "pf_params_t": (L.Params, ["E", "nu", "rho", "Gc", "l0", "eta", "gamma_star", "model", "split", "plane",
                                    "bounds"]),
         "pf_state_t": (L.StatePtrs, ["ux", "uy", "vx", "vy", "ax", "ay", "d", "H"]),
-        "pf_cg_opts_t": (L.CgOpts, ["tol", "max_iter", "check_every"]),
+        "pf_cg_opts_t": (L.CgOpts, ["tol", "max_iter", "check_every", "start", "monotone"]),
         "pf_cg_stats_t": (L.CgStats, ["iters", "restarts", "n_active", "flags", "resid"]),
         "pf_instance_info_t": (L.InstanceInfo, ["node_offset", "n_nodes", "elem_offset", "n_elems", "tile_offset",
                                                 "n_tiles", "h_min", "area"]),

@@ -48,10 +48,13 @@ def test_explicit_step_matches_oracle(dtype, split, plane):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("model", [1, 2])
-def test_damage_solve_matches_exact_qp(dtype, model):
+@pytest.mark.parametrize("monotone", [0, 1])
+def test_damage_solve_matches_exact_qp(dtype, model, monotone):
+    """Both solver flavours reach the oracle's exact minimiser over [d_prev, 1]."""
     from paper_2606_23458_amd import State
+    from paper_2606_23458_amd.sim import CgConfig, default_tol
     p = w.small_plate(30, 16, jitter=0.15, seed=4, model=model, random_diag=True)
-    sim = _sim(p, dtype)
+    sim = _sim(p, dtype, cg=CgConfig(tol=default_tol(dtype), monotone=monotone))
     r = np.random.default_rng(5)
     H = r.uniform(0, 8000.0, p.n_elems) * (r.random(p.n_elems) < 0.5)
     lb = np.where(r.random(p.n_nodes) < 0.3, r.uniform(0, 0.9, p.n_nodes), 0.0)
