@@ -110,10 +110,15 @@ typedef struct {
 
 typedef struct {
     double tol;              /* stop when max_i |r_i|/A_ii <= tol on free nodes and
-                                max_i r_i/A_ii <= tol on nodes held at the bound */
+                                no node held at a bound has a scaled residual
+                                pointing inward by more than 2 tol (held nodes
+                                are released beyond that margin) */
     int32_t max_iter;        /* matrix-vector products per solve, >= 1 */
-    int32_t check_every;     /* > 0: synchronise the stream every check_every CG
-                                rounds to stop early (the default path);
+    int32_t check_every;     /* > 0: synchronise the stream to stop early: first
+                                after as many CG rounds as the handle's previous
+                                solve of the same kind needed (8 on the first
+                                solve), then every check_every rounds (the
+                                default path);
                                 0: enqueue exactly max_iter rounds and never
                                 synchronise (suitable for HIP-graph capture) */
     int32_t start;           /* damage solve only.  0: start from d_prev;
@@ -126,6 +131,19 @@ typedef struct {
                                 held-set updates between CG runs (slower; the
                                 solver falls back to it by itself when the
                                 held set does not settle) */
+    int32_t rounds;          /* check_every = 0 only: CG rounds to enqueue
+                                (0 = max_iter); rounds of an instance that has
+                                finished do nothing */
+    int32_t resume;          /* damage solve only.  1: continue the solve left
+                                unfinished by this handle's previous
+                                pf_damage_solve call with the same arguments
+                                (no set-up pass; iterate, held set and CG
+                                scalars are kept).  Every call ends with the
+                                final pass, so d, active_out and stats always
+                                hold the current iterate.  With check_every = 0
+                                and resume, a step can be captured once as a
+                                HIP graph of a fixed number of rounds and
+                                continued, rarely, by a second graph. */
 } pf_cg_opts_t;
 
 /* Per-instance solve statistics, written to DEVICE memory by the solve. */
@@ -250,6 +268,43 @@ pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt
  */
 pf_status_t pf_cfl_dt(pf_mesh_t m, const pf_params_t* p, double factor, double* dt_out);
 
+/*
+ * Tile-size autotuning (a set-up call, not part of the method; it allocates).
+ * For each candidate owned-node count per tile it builds the tile plan of the
+ * given meshes, times `reps` explicit steps from a zero state and `reps`
+ * damage CG rounds (the four launches of one CG iteration, on a linear solve
+ * over all nodes), and scores the plan as
+ *     explicit_us + cg_rounds_per_step * cg_round_us.
+ * The smallest score wins; pass out->best as pf_tile_opts_t.tile_nodes.
+ * Candidates whose tiles need more LDS than a workgroup may use are skipped
+ * (status PF_ERR_UNSUPPORTED).  `inst`, `n_instances`, `dtype` and `p` are as
+ * for pf_mesh_create and pf_explicit_step.  Synchronous on `stream`; the
+ * result depends on the device, so callers cache it per size class.
+ */
+enum { PF_TUNE_MAX = 8 };
+
+typedef struct {
+    int32_t n_candidates;        /* entries of tile_nodes[] to try, 0..8; 0 = the default set
+                                    {128, 192, 256, 384, 512, 768, 1024} */
+    int32_t tile_nodes[PF_TUNE_MAX];
+    int32_t reps;                /* timed launches per candidate, 0..10000; 0 = 20 */
+    double cg_rounds_per_step;   /* weight of one CG round in the score; <= 0 selects 16 */
+} pf_tune_opts_t;
+
+typedef struct {
+    int32_t best;                       /* the chosen tile_nodes */
+    int32_t n_tried;                    /* candidates tried (entries filled below) */
+    int32_t tile_nodes[PF_TUNE_MAX];
+    int32_t status[PF_TUNE_MAX];        /* pf_status_t of each candidate's plan */
+    double explicit_us[PF_TUNE_MAX];    /* mean explicit-step time */
+    double cg_round_us[PF_TUNE_MAX];    /* mean damage CG round time */
+    double score_us[PF_TUNE_MAX];
+} pf_tune_result_t;
+
+pf_status_t pf_tune_tiles(const pf_mesh_desc_t* inst, int32_t n_instances, pf_dtype_t dtype,
+                          const pf_params_t* p, const pf_tune_opts_t* opts, pf_tune_result_t* out,
+                          pf_stream_t stream);
+
 /* Thread-local description of the last non-OK status on this thread. */
 const char* pf_last_error(void);
 
@@ -260,8 +315,9 @@ const char* pf_version(void);
  * Kernel timing: when enabled, every kernel launch of this handle is
  * bracketed by HIP events on its stream.  pf_timer_read synchronises the
  * stream, returns the summed milliseconds and launch count of one kernel
- * family (0 explicit step, 1 damage matvec, 2 damage update, 3 adjoint
- * kernels, 4 per-instance CG reductions) and resets that family.
+ * family (0 explicit step, 1 damage CG passes, 2 damage set-up and final
+ * passes, 3 adjoint kernels, 4 per-instance CG reductions) and resets that
+ * family.
  */
 pf_status_t pf_timer_enable(pf_mesh_t m, int32_t on);
 pf_status_t pf_timer_read(pf_mesh_t m, int32_t family, double* total_ms, int64_t* launches);

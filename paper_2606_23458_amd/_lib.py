@@ -43,7 +43,7 @@ class StatePtrs(C.Structure):
 
 class CgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32), ("start", C.c_int32),
-                ("monotone", C.c_int32)]
+                ("monotone", C.c_int32), ("rounds", C.c_int32), ("resume", C.c_int32)]
 
 
 class CgStats(C.Structure):
@@ -61,6 +61,20 @@ class Totals(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("n_nodes", C.c_int32), ("n_elems", C.c_int32),
                 ("n_tiles", C.c_int32), ("dtype", C.c_int32), ("max_tile_nodes", C.c_int32),
                 ("max_tile_elems", C.c_int32), ("tile_elems_total", C.c_int32), ("device_bytes", C.c_size_t)]
+
+
+PF_TUNE_MAX = 8
+
+
+class TuneOpts(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("tile_nodes", C.c_int32 * PF_TUNE_MAX), ("reps", C.c_int32),
+                ("cg_rounds_per_step", C.c_double)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("best", C.c_int32), ("n_tried", C.c_int32), ("tile_nodes", C.c_int32 * PF_TUNE_MAX),
+                ("status", C.c_int32 * PF_TUNE_MAX), ("explicit_us", C.c_double * PF_TUNE_MAX),
+                ("cg_round_us", C.c_double * PF_TUNE_MAX), ("score_us", C.c_double * PF_TUNE_MAX)]
 
 
 class PfError(RuntimeError):
@@ -88,6 +102,8 @@ PROTOTYPES = {
                          C.POINTER(StatePtrs), C.c_void_p, C.POINTER(StatePtrs), C.POINTER(StatePtrs),
                          C.c_void_p, C.POINTER(CgOpts), C.c_void_p, C.c_void_p],
     "pf_cfl_dt": [C.c_void_p, C.POINTER(Params), C.c_double, C.POINTER(C.c_double)],
+    "pf_tune_tiles": [C.POINTER(MeshDesc), C.c_int32, C.c_int32, C.POINTER(Params), C.POINTER(TuneOpts),
+                      C.POINTER(TuneResult), C.c_void_p],
     "pf_timer_enable": [C.c_void_p, C.c_int32],
     "pf_timer_read": [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
 }

@@ -211,7 +211,9 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
                      static_cast<T*>(m->dw.b), m->dw.wset, lam);
   timer_end(m, 3, s);
   PF_HIP(hipGetLastError());
-  pf_status_t st = damage_cg(m, CG_LINEAR, s_np1->H, lam, lam, nullptr, nullptr, o, stats, s);
+  pf_cg_opts_t oa = *o;
+  oa.resume = 0;   // every adjoint solve starts from its own set-up pass
+  pf_status_t st = damage_cg(m, CG_LINEAR, s_np1->H, lam, lam, nullptr, nullptr, &oa, stats, s);
   if (st != PF_OK) return st;
   int32_t max_loc = 0, max_te = 0;
   for (const TileRec& tr : m->tiles_h) {

@@ -13,8 +13,11 @@
 // guess (normally the previous step's flags).  After each converged CG run
 // a check pass recomputes the true residual r = b - Ax, moves free nodes that
 // left [d_prev, 1] onto the bound they crossed, and releases held nodes whose
-// scaled residual r_i/A_ii points into the interior by more than tol; the
+// scaled residual r_i/A_ii points into the interior by more than 2 tol; the
 // solve ends when a check changes nothing and the free residual passes.
+// (Releasing at tol itself lets nodes whose residual sits just above tol
+// leave one ring at a time, a check each, where the solution varies on the
+// scale of tol; the margin ends that.)
 // Each check is one primal-dual active-set update; if eight updates have not
 // settled the set, the solve switches to a monotone projected CG: steps are
 // cut at the first bound and followed by a projected Jacobi-gradient step of
@@ -25,25 +28,44 @@
 // wrong held set, e.g. the first AT1 step, would otherwise cost a solve of a
 // nearly singular free system).
 //
-// Each CG round is four launches: over the tile grid
-//   A  q = A s with s = x (restart, check) or s = p = z + beta p_old
-//      (iteration); on the first pass also assembles b and the diagonal;
-//      per-tile partial p'q (and the largest feasible step, monotone flavour);
-//   B  restart / check: r = b - q, held-set update, z = D^-1 r on free nodes;
-//      iteration: x += alpha p, r -= alpha q, z; per-tile partials;
-// and, after each, one workgroup per instance (k_dmg_reduce_a / _b) that
-// combines that instance's per-tile partials in a fixed order (so results
-// are bitwise reproducible) and advances the instance's state.  No atomics
-// and no device-wide fences are used.  Linear mode (CG_LINEAR) solves
-// A_FF x_F = b_F for a fixed held set and is used by the adjoint step.
+// Iteration.  The CG recurrences are arranged so that one iteration needs a
+// single reduction (the Chronopoulos-Gear form): with z = M r (M = D^-1 on
+// free nodes, 0 on held ones), w = A z and s = A p,
+//     p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//     z = M r,  w = A z,  gamma = r'z,  delta = z'w,
+//     beta' = gamma'/gamma,  alpha' = gamma'/(delta' - beta' gamma'/alpha).
+// One round of the solve is two launches over the tile grid:
+//   k_dmg      one pass of the current phase for every tile of every
+//              instance that is not done:
+//                restart / check: x-matvec in FP64, true residual, held-set
+//                  update (the first restart also assembles b, the diagonal
+//                  and the per-solve mass coefficients);
+//                first: z = M r and w = A z of a new CG run;
+//                iterate: the vector updates above and w = A z, where each
+//                  tile recomputes z on its halo nodes from the previous
+//                  vectors, so no second pass is needed;
+//              and per-tile partial sums;
+//   k_dmg_red  one workgroup per instance combines its tiles' partials in a
+//              fixed order (bitwise reproducible results) and advances the
+//              instance's state.
+// r, w, s and x are ping-pong pairs: a pass reads one half and writes the
+// other, so halo reads never race with the owners' writes.  No atomics and no
+// device-wide fences are used.  Linear mode (CG_LINEAR) solves A_FF x_F = b_F
+// for a fixed held set and is used by the adjoint step.
 #include "device_common.hpp"
 
 namespace pf {
 
 constexpr int kSwitchAfter = 8;        // active-set updates before the monotone fallback
 constexpr double kExpandStep = 0.25;   // projected-gradient step of the fallback
+constexpr double kRelease = 2.0;       // held nodes are released when their scaled residual
+                                       // points inward by more than kRelease * tol
 
-enum { HELD_NONE = 0, HELD_LOWER = 1, HELD_UPPER = 2 };
+// held-set states; HELD_FIXED: d_prev = 1, the node cannot move
+enum { HELD_NONE = 0, HELD_LOWER = 1, HELD_UPPER = 2, HELD_FIXED = 3 };
+
+// partial sums of one tile
+enum { PT_DELTA = 0, PT_AMIN = 1, PT_GAMMA = 2, PT_CF = 3, PT_CA = 4, PT_NA = 5, PT_RB = 6, PT_CH = 7 };
 
 template <typename T>
 struct DmgArgs {
@@ -54,11 +76,15 @@ struct DmgArgs {
   const T* __restrict__ H;
   const T* __restrict__ lb;
   const uint8_t* __restrict__ guess;
-  T* x;                // the iterate (a workspace for the damage solve)
+  T* x0; T* x1;        // iterate pair (QP: workspaces; linear: the caller's x and a workspace)
+  T* r0; T* r1;        // residual pair
+  T* w0; T* w1;        // A z pair
+  T* s0; T* s1;        // A p pair
+  T* p;                // search direction (read and written by the owner only)
   T* dout;             // damage solve: output array (read at set-up when start = 1)
   T* mte;              // per-solve mass coefficient of each tile element
-  T* b; T* dinv; T* r; T* z; T* p0; T* p1; T* q;
-  uint8_t* W;
+  T* b; T* dinv;
+  uint8_t* W0; uint8_t* W1;   // held-set pair (flipped by restart and check passes)
   double tol;
   int32_t max_iter;
   int32_t kind;        // CG_QP or CG_LINEAR
@@ -78,6 +104,7 @@ __global__ void k_dmg_init(Ctl* ctl, int n_inst, int kind, int monotone) {
   c.flags = 0;
   c.nact = 0;
   c.pbuf = 0;
+  c.wbuf = 0;
   c.flavor = (kind == CG_QP && monotone) ? 1 : 0;
   c.outer = 0;
   c.inner = 0;
@@ -96,33 +123,57 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dmg_a(DmgArgs<T> a) {
+__global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[kWaves];
   const TileRec t = a.dm.tiles[blockIdx.x];
   const Ctl* c = a.ctl + t.inst;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
   const InstP<T> P = a.ip[t.inst];
-  const bool matvec_x = (mode != MODE_ITER);
-  const bool setup = matvec_x && (c->setup != 0);
   const bool qp = (a.kind == CG_QP);
   const bool projected = qp && (P.bounds == PF_BOUNDS_PROJECTED);
   const bool monotone = projected && (c->flavor != 0);
-  const double beta = c->beta;
-  const int pb = c->pbuf;
-  const T* pold = pb ? a.p1 : a.p0;
-  T* pnew = pb ? a.p0 : a.p1;
+  const bool xpass = (mode == MODE_RESTART || mode == MODE_CHECK);
+  const bool iter = (mode == MODE_ITER);
+  const bool setup = xpass && (c->setup != 0);
+  const bool cut = xpass && (c->hit != 0);
+  const bool release = c->release != 0;
+  const bool cur1 = c->pbuf != 0;
+  const double alpha = c->alpha, beta = c->beta, amax = c->amax;
+  const T al = T(alpha), be = T(beta);
+  const double tol = a.tol;
+  // current halves (read) and next halves (written) of the pairs
+  const T* __restrict__ xc = cur1 ? a.x1 : a.x0;
+  const T* __restrict__ rc = cur1 ? a.r1 : a.r0;
+  const T* __restrict__ wc = cur1 ? a.w1 : a.w0;
+  const T* __restrict__ sc = cur1 ? a.s1 : a.s0;
+  T* xn_ = cur1 ? a.x0 : a.x1;
+  T* rn_ = cur1 ? a.r0 : a.r1;
+  T* wn_ = cur1 ? a.w0 : a.w1;
+  T* sn_ = cur1 ? a.s0 : a.s1;
+  const bool wcur1 = c->wbuf != 0;
+  const uint8_t* __restrict__ Wc = wcur1 ? a.W1 : a.W0;
+  uint8_t* Wn = wcur1 ? a.W0 : a.W1;
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
-  T* s = reinterpret_cast<T*>(smem);
-  T* qc = s + nloc;                 // [3 n_telem] corner values of A^e s^e
-  T* dc = qc + 3 * t.n_telem;       // [3 n_telem] diagonal corners (first pass)
-  T* bc = dc + 3 * t.n_telem;       // [n_telem]   load per corner (first pass, QP)
+  T* sv = reinterpret_cast<T*>(smem);          // [nloc] the vector the pass multiplies by A
+  // after sv (8-byte aligned): iteration passes keep the element corner values
+  // of A^e z^e in T; restart and check passes keep them in FP64 (the true
+  // residual is then accurate to the rounding of x, not of an FP32 matvec);
+  // the set-up sweep first uses the same space for diagonal corners and loads
+  unsigned char* rest = smem + ((size_t(nloc) * sizeof(T) + 7) & ~size_t(7));
+  T* qc = reinterpret_cast<T*>(rest);          // [3 n_telem] (first, iterate)
+  double* qd = reinterpret_cast<double*>(rest); // [3 n_telem] (restart, check)
+  T* dc = reinterpret_cast<T*>(rest);          // [3 n_telem] diagonal corners (set-up)
+  T* bc = dc + 3 * t.n_telem;                  // [n_telem]   load per corner (set-up, QP)
   const int tid = threadIdx.x;
 
+  // ---- phase 1: the vector to multiply, on owned and halo nodes -------------
+  double amin = INFINITY, ch = 0.0;
   for (int i = tid; i < nloc; i += kBlock) {
-    const int g = (i < t.n_own) ? t.node_begin + i : a.dm.halo_idx[t.halo_begin + (i - t.n_own)];
+    const bool own = i < t.n_own;
+    const int g = own ? t.node_begin + i : a.dm.halo_idx[t.halo_begin + (i - t.n_own)];
     T v;
     if (setup && qp) {
       // start at d_prev (or its extrapolation in time), or at 1 where the guess
@@ -135,58 +186,71 @@ __global__ __launch_bounds__(kBlock) void k_dmg_a(DmgArgs<T> a) {
       } else {
         v = lbv;
       }
-      if (i < t.n_own) a.x[g] = v;
-    } else if (matvec_x) {
-      v = a.x[g];
+    } else if (xpass) {
+      v = xc[g];
+      if (cut && Wc[g] == HELD_NONE) {
+        // monotone flavour: the last step cut at the first bound (step amax
+        // along p, whose A p is in the other half of the s pair), then a
+        // projected Jacobi-gradient step
+        const T am = T(amax);
+        const T xh = v + am * a.p[g];
+        const T rh = rc[g] - am * sn_[g];
+        v = clamp01<T>(xh + T(kExpandStep) * a.dinv[g] * rh, a.lb[g]);
+      }
+    } else if (!iter) {
+      v = Wc[g] ? T(0) : a.dinv[g] * rc[g];    // first pass of a CG run: z = M r
     } else {
-      const T zz = a.z[g];
-      v = (beta == 0.0) ? zz : zz + T(beta) * pold[g];
-      if (i < t.n_own) pnew[g] = v;
+      const uint8_t wf = Wc[g];
+      const T di = a.dinv[g];
+      const T rv = rc[g];
+      const T sn = (beta == 0.0) ? wc[g] : wc[g] + be * sc[g];   // s = A p of this iteration
+      const T rn = rv - al * sn;
+      v = wf ? T(0) : di * rn;                                   // z of the next iteration
+      if (own) {
+        const T zv = wf ? T(0) : di * rv;
+        const T pv = (beta == 0.0) ? zv : zv + be * a.p[g];
+        const T xv = xc[g];
+        T xn = xv + al * pv;
+        if (monotone && !wf) {
+          // largest step that keeps this node inside [d_prev, 1]
+          const double lbv = double(a.lb[g]);
+          if (pv < T(0)) amin = fmin(amin, (lbv - double(xv)) / double(pv));
+          if (pv > T(0)) amin = fmin(amin, (1.0 - double(xv)) / double(pv));
+          xn = clamp01<T>(xn, T(lbv));
+        } else if (projected && !wf) {
+          const double xd = double(xn);
+          if (double(a.lb[g]) - xd > tol || xd - 1.0 > tol) ch += 1.0;   // free node outside the bounds
+        }
+        a.p[g] = pv;
+        sn_[g] = sn;
+        xn_[g] = xn;
+        rn_[g] = rn;
+      }
     }
-    s[i] = v;
+    sv[i] = v;
   }
-  __syncthreads();
 
+  // ---- set-up: load vector, Jacobi diagonal, per-solve mass coefficients ----
   const T* __restrict__ geo = static_cast<const T*>(a.dm.geo);
   const size_t nte = size_t(a.dm.n_te);
-  for (int e = tid; e < t.n_telem; e += kBlock) {
-    const int te = t.telem_begin + e;
-    const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
-    const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-    const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-    const T kA = P.kap * A;
-    T mA, He = T(0);
-    if (setup) {
-      He = a.H[a.dm.te_gid[te]];
-      mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
+  if (setup) {
+    for (int e = tid; e < t.n_telem; e += kBlock) {
+      const int te = t.telem_begin + e;
+      const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+      const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+      const T kA = P.kap * A;
+      const T He = a.H[a.dm.te_gid[te]];
+      const T mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
       a.mte[te] = mA;
-    } else {
-      mA = a.mte[te];
-    }
-    const T s0 = s[c0], s1 = s[c1], s2 = s[c2];
-    const T gpx = g0x * s0 + g1x * s1 + g2x * s2;
-    const T gpy = g0y * s0 + g1y * s1 + g2y * s2;
-    const T ss = s0 + s1 + s2;
-    qc[3 * e + 0] = kA * (g0x * gpx + g0y * gpy) + mA * (s0 + ss);
-    qc[3 * e + 1] = kA * (g1x * gpx + g1y * gpy) + mA * (s1 + ss);
-    qc[3 * e + 2] = kA * (g2x * gpx + g2y * gpy) + mA * (s2 + ss);
-    if (setup) {
       dc[3 * e + 0] = kA * (g0x * g0x + g0y * g0y) + T(2) * mA;
       dc[3 * e + 1] = kA * (g1x * g1x + g1y * g1y) + T(2) * mA;
       dc[3 * e + 2] = kA * (g2x * g2x + g2y * g2y) + T(2) * mA;
       bc[e] = qp ? (P.b0 + P.bH * He) * A * T(1.0 / 3.0) : T(0);
     }
-  }
-  __syncthreads();
-
-  double pq = 0.0, amin = INFINITY;
-  for (int i = tid; i < t.n_own; i += kBlock) {
-    const int g = t.node_begin + i;
-    const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
-    T qi = T(0);
-    for (int j = j0; j < j1; ++j) qi += qc[a.dm.lcorner[j]];
-    a.q[g] = qi;
-    if (setup) {
+    __syncthreads();
+    for (int i = tid; i < t.n_own; i += kBlock) {
+      const int g = t.node_begin + i;
+      const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
       T di = T(0), bi = T(0);
       for (int j = j0; j < j1; ++j) {
         const int cc = a.dm.lcorner[j];
@@ -196,95 +260,69 @@ __global__ __launch_bounds__(kBlock) void k_dmg_a(DmgArgs<T> a) {
       if (qp) a.b[g] = bi;
       a.dinv[g] = T(1) / di;
     }
-    if (!matvec_x) {
-      const T pv = s[i];
-      pq += double(pv) * double(qi);
-      if (monotone && a.W[g] == HELD_NONE) {
-        // largest step that keeps this node inside [d_prev, 1]
-        if (pv < T(0)) amin = fmin(amin, (double(a.lb[g]) - double(a.x[g])) / double(pv));
-        if (pv > T(0)) amin = fmin(amin, (1.0 - double(a.x[g])) / double(pv));
-      }
+  }
+  __syncthreads();
+
+  // ---- phase 2: element corner values of A^e v^e ----------------------------
+  for (int e = tid; e < t.n_telem; e += kBlock) {
+    const int te = t.telem_begin + e;
+    const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
+    const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+    const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+    const T kA = P.kap * A;
+    const T mA = a.mte[te];
+    if (xpass) {
+      const double s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
+      const double gpx = double(g0x) * s0 + double(g1x) * s1 + double(g2x) * s2;
+      const double gpy = double(g0y) * s0 + double(g1y) * s1 + double(g2y) * s2;
+      const double ss = s0 + s1 + s2;
+      const double k = kA, mm = mA;
+      qd[3 * e + 0] = k * (double(g0x) * gpx + double(g0y) * gpy) + mm * (s0 + ss);
+      qd[3 * e + 1] = k * (double(g1x) * gpx + double(g1y) * gpy) + mm * (s1 + ss);
+      qd[3 * e + 2] = k * (double(g2x) * gpx + double(g2y) * gpy) + mm * (s2 + ss);
+    } else {
+      const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
+      const T gpx = g0x * s0 + g1x * s1 + g2x * s2;
+      const T gpy = g0y * s0 + g1y * s1 + g2y * s2;
+      const T ss = s0 + s1 + s2;
+      qc[3 * e + 0] = kA * (g0x * gpx + g0y * gpy) + mA * (s0 + ss);
+      qc[3 * e + 1] = kA * (g1x * gpx + g1y * gpy) + mA * (s1 + ss);
+      qc[3 * e + 2] = kA * (g2x * gpx + g2y * gpy) + mA * (s2 + ss);
     }
   }
-  if (matvec_x) return;   // restart and check passes reduce in kernel B
-  pq = block_sum(pq, red);
-  amin = block_min(amin, red);
-  if (tid == 0) {
-    a.part[8 * blockIdx.x + 0] = pq;
-    a.part[8 * blockIdx.x + 1] = amin;
-  }
-}
+  __syncthreads();
 
-// One workgroup per instance: step length of the current iteration.
-__global__ __launch_bounds__(kBlock) void k_dmg_reduce_a(Ctl* ctl, const double* part) {
-  __shared__ double red[kWaves];
-  Ctl* c = ctl + blockIdx.x;
-  if (c->mode != MODE_ITER) return;
-  double sq = 0.0, sm = INFINITY;
-  for (int k = threadIdx.x; k < c->ntiles; k += kBlock) {
-    sq += part[8 * (c->tile0 + k) + 0];
-    sm = fmin(sm, part[8 * (c->tile0 + k) + 1]);
-  }
-  sq = block_sum(sq, red);
-  sm = block_min(sm, red);
-  if (threadIdx.x != 0) return;
-  double alpha = c->rz / sq;
-  int hit = 0;
-  if (!(sq > 0.0) || !isfinite(alpha)) {
-    c->flags |= PF_FLAG_NONFINITE;
-    c->mode = MODE_DONE;
-    alpha = 0.0;
-  } else if (sm <= alpha) {
-    alpha = sm;
-    hit = 1;
-  }
-  c->pq = sq;
-  c->amax = sm;
-  c->alpha = alpha;
-  c->hit = hit;
-  c->pbuf ^= 1;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dmg_b(DmgArgs<T> a) {
-  __shared__ double red[kWaves];
-  const TileRec t = a.dm.tiles[blockIdx.x];
-  const Ctl* c = a.ctl + t.inst;
-  const int mode = c->mode;
-  if (mode == MODE_DONE) return;
-  const InstP<T> P = a.ip[t.inst];
-  const bool qp = (a.kind == CG_QP);
-  const bool projected = qp && (P.bounds == PF_BOUNDS_PROJECTED);
-  const bool monotone = projected && (c->flavor != 0);
-  const bool setup = c->setup != 0;
-  const double tol = a.tol;
-  const int tid = threadIdx.x;
-  // partials: rz, max free |r|/A_ii, max held "wants to leave" r/A_ii, held count, max |b|/A_ii, changes
-  double rz = 0.0, cf = 0.0, ca = -INFINITY, na = 0.0, rb = 0.0, ch = 0.0;
-  if (mode != MODE_ITER) {
-    const bool release = c->release != 0;
+  // ---- phase 3: gather per owned node, then the pass's node work -----------
+  // partials: gamma = r'z, delta = z'Az, max free |r|/A_ii, max held "wants
+  // to leave" r/A_ii, held count, max |b|/A_ii (linear set-up), changes
+  double gam = 0.0, del = 0.0, cf = 0.0, ca = -INFINITY, na = 0.0, rb = 0.0;
+  if (xpass) {
     for (int i = tid; i < t.n_own; i += kBlock) {
       const int g = t.node_begin + i;
+      const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+      double qi = 0.0;
+      for (int j = j0; j < j1; ++j) qi += qd[a.dm.lcorner[j]];
       const T bi = a.b[g];
-      const T ri = bi - a.q[g];
+      const T ri = T(double(bi) - qi);
       const T di = a.dinv[g];
       const double sr = double(ri) * double(di);
+      T xv = sv[i];
       uint8_t w = HELD_NONE;
       if (!qp) {
-        w = a.W[g];
+        w = Wc[g];
         if (setup && w == HELD_NONE) rb = fmax(rb, fabs(double(bi) * double(di)));
       } else if (projected) {
-        const T xv = a.x[g], lbv = a.lb[g];
-        const uint8_t wold = a.W[g];
+        const T lbv = a.lb[g];
+        const uint8_t wold = Wc[g];
         if (lbv >= T(1)) {
-          w = HELD_LOWER;   // d_prev = 1: the node is fixed
+          w = HELD_FIXED;   // d_prev = 1: the node is fixed
         } else if (mode == MODE_CHECK) {
           const bool viol_lo = wold == HELD_NONE && double(lbv) - double(xv) > tol;
           const bool viol_up = wold == HELD_NONE && double(xv) - 1.0 > tol;
-          const bool rel = (wold == HELD_LOWER && sr > tol) || (wold == HELD_UPPER && sr < -tol);
+          const bool rel = (wold == HELD_LOWER && sr > kRelease * tol) || (wold == HELD_UPPER && sr < -kRelease * tol);
           w = viol_lo ? HELD_LOWER : (viol_up ? HELD_UPPER : (rel ? HELD_NONE : wold));
-          if (viol_lo) a.x[g] = lbv;
-          if (viol_up) a.x[g] = T(1);
+          if (viol_lo) xv = lbv;
+          if (viol_up) xv = T(1);
           ch += (viol_lo || viol_up || rel) ? 1.0 : 0.0;
         } else if (setup) {
           const uint8_t gs = a.guess ? a.guess[g] : uint8_t(0);
@@ -293,66 +331,46 @@ __global__ __launch_bounds__(kBlock) void k_dmg_b(DmgArgs<T> a) {
         } else if (!monotone) {
           w = wold;
         } else {
-          const bool want_lo = ri < T(0) || (wold == HELD_LOWER && !(release && sr > tol));
-          const bool want_up = ri > T(0) || (wold == HELD_UPPER && !(release && sr < -tol));
+          const bool want_lo = ri < T(0) || (wold == HELD_LOWER && !(release && sr > kRelease * tol));
+          const bool want_up = ri > T(0) || (wold == HELD_UPPER && !(release && sr < -kRelease * tol));
           w = (xv <= lbv && want_lo) ? HELD_LOWER : ((xv >= T(1) && want_up) ? HELD_UPPER : HELD_NONE);
         }
       }
-      const T zi = w ? T(0) : di * ri;
-      a.r[g] = ri;
-      a.z[g] = zi;
-      a.W[g] = w;
-      rz += double(ri) * double(zi);
+      xn_[g] = xv;
+      rn_[g] = ri;
+      Wn[g] = w;
       if (w) {
-        ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
+        if (w != HELD_FIXED) ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
         na += 1.0;
       } else {
         cf = fmax(cf, fabs(sr));
       }
     }
   } else {
-    const double alpha = c->alpha;
-    const bool hit = c->hit != 0;
-    const T* p = c->pbuf ? a.p1 : a.p0;
-    const T al = T(alpha);
+    T* wn = iter ? wn_ : (cur1 ? a.w1 : a.w0);
+    const T* rz = iter ? rn_ : rc;
     for (int i = tid; i < t.n_own; i += kBlock) {
       const int g = t.node_begin + i;
-      const T pv = p[g];
-      const T xv = a.x[g];
-      const uint8_t w = a.W[g];
-      const T qv = a.q[g];
-      const T di = a.dinv[g];
-      if (hit) {
-        // monotone flavour: step to the first bound, then a projected Jacobi-gradient step
-        if (!w) {
-          const T xh = xv + al * pv;
-          const T rh = a.r[g] - al * qv;
-          a.x[g] = clamp01<T>(xh + T(kExpandStep) * di * rh, a.lb[g]);
-        }
-        continue;
-      }
-      T xn = xv + al * pv;
-      if (monotone) {
-        xn = clamp01<T>(xn, a.lb[g]);
-      } else if (projected && !w) {
-        const double xd = double(xn);
-        if (double(a.lb[g]) - xd > tol || xd - 1.0 > tol) ch += 1.0;   // free node outside the bounds
-      }
-      a.x[g] = xn;
-      const T ri = a.r[g] - al * qv;
-      const T zi = w ? T(0) : di * ri;
-      a.r[g] = ri;
-      a.z[g] = zi;
-      rz += double(ri) * double(zi);
-      const double sr = double(ri) * double(di);
+      const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+      T qi = T(0);
+      for (int j = j0; j < j1; ++j) qi += qc[a.dm.lcorner[j]];
+      wn[g] = qi;
+      const T zv = sv[i];
+      const T rv = rz[g];
+      gam += double(rv) * double(zv);
+      del += double(zv) * double(qi);
+      const double sr = double(rv) * double(a.dinv[g]);
+      const uint8_t w = Wc[g];
       if (w) {
-        ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
+        if (w != HELD_FIXED) ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
       } else {
         cf = fmax(cf, fabs(sr));
       }
     }
   }
-  rz = block_sum(rz, red);
+  del = block_sum(del, red);
+  amin = block_min(amin, red);
+  gam = block_sum(gam, red);
   cf = block_max(cf, red);
   ca = block_max(ca, red);
   na = block_sum(na, red);
@@ -360,33 +378,39 @@ __global__ __launch_bounds__(kBlock) void k_dmg_b(DmgArgs<T> a) {
   ch = block_sum(ch, red);
   if (tid == 0) {
     double* pp = a.part + 8 * blockIdx.x;
-    pp[2] = rz;
-    pp[3] = cf;
-    pp[4] = ca;
-    pp[5] = na;
-    pp[6] = rb;
-    pp[7] = ch;
+    pp[PT_DELTA] = del;
+    pp[PT_AMIN] = amin;
+    pp[PT_GAMMA] = gam;
+    pp[PT_CF] = cf;
+    pp[PT_CA] = ca;
+    pp[PT_NA] = na;
+    pp[PT_RB] = rb;
+    pp[PT_CH] = ch;
   }
 }
 
-// One workgroup per instance: combine kernel B's partials and advance the state.
-__global__ __launch_bounds__(kBlock) void k_dmg_reduce_b(Ctl* ctl, const double* part, const int* bounds, int kind,
-                                                         double tol, int max_iter) {
+// One workgroup per instance: combine the tiles' partials and advance the state.
+__global__ __launch_bounds__(kBlock) void k_dmg_red(Ctl* ctl, const double* part, const int* bounds, int kind,
+                                                    double tol, int max_iter) {
   __shared__ double red[kWaves];
   Ctl* c = ctl + blockIdx.x;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
-  double srz = 0.0, scf = 0.0, sca = -INFINITY, sna = 0.0, srb = 0.0, sch = 0.0;
+  double sdel = 0.0, samin = INFINITY, sgam = 0.0, scf = 0.0, sca = -INFINITY, sna = 0.0, srb = 0.0, sch = 0.0;
   for (int k = threadIdx.x; k < c->ntiles; k += kBlock) {
     const double* pp = part + 8 * (c->tile0 + k);
-    srz += pp[2];
-    scf = fmax(scf, pp[3]);
-    sca = fmax(sca, pp[4]);
-    sna += pp[5];
-    srb = fmax(srb, pp[6]);
-    sch += pp[7];
+    sdel += pp[PT_DELTA];
+    samin = fmin(samin, pp[PT_AMIN]);
+    sgam += pp[PT_GAMMA];
+    scf = fmax(scf, pp[PT_CF]);
+    sca = fmax(sca, pp[PT_CA]);
+    sna += pp[PT_NA];
+    srb = fmax(srb, pp[PT_RB]);
+    sch += pp[PT_CH];
   }
-  srz = block_sum(srz, red);
+  sdel = block_sum(sdel, red);
+  samin = block_min(samin, red);
+  sgam = block_sum(sgam, red);
   scf = block_max(scf, red);
   sca = block_max(sca, red);
   sna = block_sum(sna, red);
@@ -402,11 +426,15 @@ __global__ __launch_bounds__(kBlock) void k_dmg_reduce_b(Ctl* ctl, const double*
   if (setup && !qp) c->ref = srb;   // linear solves stop relative to max |b_i|/A_ii
   const double tl = tol * c->ref;
   const double rs = c->ref > 0.0 ? c->ref : 1.0;
-  if (mode != MODE_ITER) {
+  if (mode == MODE_RESTART || mode == MODE_CHECK) {
+    // the pass wrote x, r and the held set into the other halves of their pairs
+    c->pbuf ^= 1;
+    c->wbuf ^= 1;
     c->setup = 0;
+    c->hit = 0;
     c->nact = int32_t(sna);
     c->resid = (monotone ? fmax(scf, sca) : scf) / rs;
-    if (!isfinite(srz) || !isfinite(scf)) {
+    if (!isfinite(scf)) {
       c->flags |= PF_FLAG_NONFINITE;
       c->mode = MODE_DONE;
     } else if (!qp && c->ref == 0.0) {
@@ -421,51 +449,69 @@ __global__ __launch_bounds__(kBlock) void k_dmg_reduce_b(Ctl* ctl, const double*
       } else if (scf <= tl) {
         c->mode = MODE_DONE;
       } else {
-        c->mode = MODE_ITER;
-        c->beta = 0.0;
-        c->rz = srz;
+        c->mode = MODE_FIRST;
       }
     } else if (monotone) {
-      if (scf <= tl && sca <= tl) {
+      if (scf <= tl && sca <= kRelease * tl) {
         c->mode = MODE_DONE;
       } else if (scf <= tl) {
         c->mode = MODE_RESTART;   // face converged, held nodes want to leave: release them
         c->release = 1;
         c->restarts += 1;
       } else {
-        c->mode = MODE_ITER;
-        c->beta = 0.0;
-        c->rz = srz;
+        c->mode = MODE_FIRST;
       }
     } else if (scf <= tl) {
       c->mode = projected ? MODE_CHECK : MODE_DONE;
     } else {
-      c->mode = MODE_ITER;
-      c->beta = 0.0;
-      c->rz = srz;
+      c->mode = MODE_FIRST;
     }
-  } else if (c->hit) {
-    c->mode = MODE_RESTART;
+  } else if (mode == MODE_FIRST) {
+    if (!isfinite(sgam) || !isfinite(sdel)) {
+      c->flags |= PF_FLAG_NONFINITE;
+      c->mode = MODE_DONE;
+    } else if (!(sdel > 0.0)) {
+      // z = 0 on every free node: the free residual vanishes
+      c->mode = projected && !monotone ? MODE_CHECK : MODE_RESTART;
+      c->release = monotone ? 1 : 0;
+    } else {
+      c->alpha = sgam / sdel;
+      c->beta = 0.0;
+      c->rz = sgam;
+      c->mode = MODE_ITER;
+    }
+  } else if (monotone && samin < c->alpha) {
+    // the step crosses a bound: cut it there and restart (x, r stay in the
+    // current halves; p and s = A p of this step are kept for the cut)
+    c->amax = fmax(samin, 0.0);
+    c->hit = 1;
     c->release = 0;
     c->restarts += 1;
-  } else if (!isfinite(srz)) {
-    c->flags |= PF_FLAG_NONFINITE;
-    c->mode = MODE_DONE;
+    c->mode = MODE_RESTART;
   } else {
-    c->beta = srz / c->rz;
-    c->rz = srz;
+    c->pbuf ^= 1;
     c->resid = scf / rs;
+    const double beta = sgam / c->rz;
+    const double den = sdel - beta * sgam / c->alpha;
     const bool early = projected && !monotone && c->inner >= 2 && sch > 0.25 * double(c->nnodes - c->nact);
-    if (scf <= tl || srz == 0.0 || early) {
-      // this CG run converged on its recurrence residual, or a quarter of the
-      // free nodes already left their bounds: update the held set now
+    if (!isfinite(sgam) || !isfinite(sdel)) {
+      c->flags |= PF_FLAG_NONFINITE;
+      c->mode = MODE_DONE;
+    } else if (scf <= tl || sgam == 0.0 || early || !(den > 0.0)) {
+      // this CG run converged on its recurrence residual, a quarter of the
+      // free nodes already left their bounds, or the recurrence lost
+      // definiteness: recompute the true residual (and update the held set)
       if (projected && !monotone) {
         c->mode = MODE_CHECK;
       } else {
         c->mode = MODE_RESTART;
-        c->release = (monotone && sca > tl) ? 1 : 0;
+        c->release = (monotone && sca > kRelease * tl) ? 1 : 0;
         c->restarts += monotone ? 1 : 0;
       }
+    } else {
+      c->beta = beta;
+      c->alpha = sgam / den;
+      c->rz = sgam;
     }
   }
   if (c->mode != MODE_DONE && c->iters >= max_iter) {
@@ -481,18 +527,23 @@ __global__ __launch_bounds__(kBlock) void k_dmg_final(DmgArgs<T> a, uint8_t* act
   const Ctl* c = a.ctl + t.inst;
   const InstP<T> P = a.ip[t.inst];
   const bool projected = (P.bounds == PF_BOUNDS_PROJECTED);
+  const T* xc = c->pbuf ? a.x1 : a.x0;
+  const uint8_t* Wc = c->wbuf ? a.W1 : a.W0;
   if (a.kind != CG_QP) {
-    if (c->ref == 0.0)
-      for (int i = threadIdx.x; i < t.n_own; i += kBlock) a.x[t.node_begin + i] = T(0);
+    // the result goes to the caller's array x0
+    for (int i = threadIdx.x; i < t.n_own; i += kBlock) {
+      const int g = t.node_begin + i;
+      a.x0[g] = (c->ref == 0.0) ? T(0) : xc[g];
+    }
   } else {
     for (int i = threadIdx.x; i < t.n_own; i += kBlock) {
       const int g = t.node_begin + i;
-      T xv = a.x[g];
+      T xv = xc[g];
       const T lbv = a.lb[g];
       uint8_t act = 0;
       if (projected) {
-        const uint8_t w = a.W[g];
-        act = (w == HELD_LOWER) ? PF_ACTIVE_LOWER : ((w == HELD_UPPER) ? PF_ACTIVE_UPPER : 0);
+        const uint8_t w = Wc[g];
+        act = (w == HELD_LOWER || w == HELD_FIXED) ? PF_ACTIVE_LOWER : ((w == HELD_UPPER) ? PF_ACTIVE_UPPER : 0);
         xv = clamp01<T>(xv, lbv);   // free nodes within tol outside the bounds
       } else {
         if (xv < lbv) {
@@ -533,17 +584,22 @@ static DmgArgs<T> dmg_args(pf_mesh_s* m, int kind, const void* H, const void* d_
   a.H = static_cast<const T*>(H);
   a.lb = static_cast<const T*>(d_prev);
   a.guess = guess;
-  // the damage solve iterates in a workspace and writes d at the end; linear solves iterate in place
-  a.x = (kind == CG_QP) ? static_cast<T*>(m->dw.xw) : static_cast<T*>(d);
+  // the damage solve iterates in workspaces and writes d at the end; linear
+  // solves start from, and end in, the caller's array
+  a.x0 = (kind == CG_QP) ? static_cast<T*>(m->dw.xw0) : static_cast<T*>(d);
+  a.x1 = static_cast<T*>(m->dw.xw1);
   a.dout = static_cast<T*>(d);
+  a.r0 = static_cast<T*>(m->dw.r0);
+  a.r1 = static_cast<T*>(m->dw.r1);
+  a.w0 = static_cast<T*>(m->dw.w0);
+  a.w1 = static_cast<T*>(m->dw.w1);
+  a.s0 = static_cast<T*>(m->dw.s0);
+  a.s1 = static_cast<T*>(m->dw.s1);
+  a.p = static_cast<T*>(m->dw.p);
   a.b = static_cast<T*>(m->dw.b);
   a.dinv = static_cast<T*>(m->dw.dinv);
-  a.r = static_cast<T*>(m->dw.r);
-  a.z = static_cast<T*>(m->dw.z);
-  a.p0 = static_cast<T*>(m->dw.p0);
-  a.p1 = static_cast<T*>(m->dw.p1);
-  a.q = static_cast<T*>(m->dw.q);
-  a.W = m->dw.wset;
+  a.W0 = m->dw.wset;
+  a.W1 = m->dw.wset + m->n_nodes;
   a.tol = tol;
   a.max_iter = max_iter;
   return a;
@@ -556,28 +612,30 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
   DmgArgs<T> a = dmg_args<T>(m, kind, H, d_prev, d, guess, o->tol, o->max_iter, o->start);
   const dim3 grid(m->n_tiles), block(kBlock), igrid(m->n_inst);
   const size_t lds = m->max_lds_damage;
-  hipLaunchKernelGGL(k_dmg_init, dim3((m->n_inst + 63) / 64), dim3(64), 0, s, m->dw.ctl, m->n_inst, kind, o->monotone);
+  if (!o->resume) {
+    timer_begin(m, 2, s);
+    hipLaunchKernelGGL(k_dmg_init, dim3((m->n_inst + 63) / 64), dim3(64), 0, s, m->dw.ctl, m->n_inst, kind,
+                       o->monotone);
+    timer_end(m, 2, s);
+  }
   auto round = [&]() {
     timer_begin(m, 1, s);
-    hipLaunchKernelGGL(k_dmg_a<T>, grid, block, lds, s, a);
+    hipLaunchKernelGGL(k_dmg<T>, grid, block, lds, s, a);
     timer_end(m, 1, s);
     timer_begin(m, 4, s);
-    hipLaunchKernelGGL(k_dmg_reduce_a, igrid, block, 0, s, m->dw.ctl, m->dw.part);
-    timer_end(m, 4, s);
-    timer_begin(m, 2, s);
-    hipLaunchKernelGGL(k_dmg_b<T>, grid, block, 0, s, a);
-    timer_end(m, 2, s);
-    timer_begin(m, 4, s);
-    hipLaunchKernelGGL(k_dmg_reduce_b, igrid, block, 0, s, m->dw.ctl, m->dw.part, m->dw.bounds, kind, o->tol,
+    hipLaunchKernelGGL(k_dmg_red, igrid, block, 0, s, m->dw.ctl, m->dw.part, m->dw.bounds, kind, o->tol,
                        o->max_iter);
     timer_end(m, 4, s);
   };
-  const int max_rounds = o->max_iter;
+  const int max_rounds = (o->check_every <= 0 && o->rounds > 0) ? std::min(o->rounds, o->max_iter) : o->max_iter;
   int launched = 0;
   if (o->check_every <= 0) {
     for (; launched < max_rounds; ++launched) round();
   } else {
-    int chunk = std::min(o->check_every, 8);
+    // first poll after as many rounds as the last solve of this kind needed
+    // (solves of consecutive steps take similar counts), then every check_every
+    const int last = m->last_rounds[kind == CG_QP ? 0 : 1];
+    int chunk = last > 0 ? std::min(std::max(last, 2), 64) : std::min(o->check_every, 8);
     while (launched < max_rounds) {
       const int n = std::min(chunk, max_rounds - launched);
       for (int k = 0; k < n; ++k) round();
@@ -591,16 +649,20 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
       chunk = std::max(chunk, o->check_every);
     }
   }
+  timer_begin(m, 2, s);
   hipLaunchKernelGGL(k_dmg_final<T>, grid, block, 0, s, a, active_out, stats);
+  timer_end(m, 2, s);
   PF_HIP(hipGetLastError());
   if (o->check_every > 0) {
     PF_HIP(hipMemcpyAsync(m->ctl_pinned, m->dw.ctl, sizeof(Ctl) * m->n_inst, hipMemcpyDeviceToHost, s));
     PF_HIP(hipStreamSynchronize(s));
-    int flags = 0;
+    int flags = 0, rounds = 0;
     for (int k = 0; k < m->n_inst; ++k) {
       flags |= m->ctl_pinned[k].flags;
       if (m->ctl_pinned[k].mode != MODE_DONE) flags |= PF_FLAG_NOT_CONVERGED;
+      rounds = std::max(rounds, int(m->ctl_pinned[k].iters));
     }
+    m->last_rounds[kind == CG_QP ? 0 : 1] = rounds;
     if (flags & PF_FLAG_NONFINITE) return fail(PF_ERR_NONFINITE, "non-finite value in the damage CG");
     if (flags & PF_FLAG_NOT_CONVERGED) return fail(PF_ERR_NOT_CONVERGED, "damage CG reached max_iter");
   }
@@ -626,7 +688,10 @@ extern "C" pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const 
   if (!H || !d_prev || !d || !opts) return fail(PF_ERR_ARG, "NULL argument");
   if (d == d_prev) return fail(PF_ERR_ARG, "d must not alias d_prev");
   if (!(opts->tol > 0) || opts->max_iter < 1) return fail(PF_ERR_ARG, "need tol > 0 and max_iter >= 1");
+  if (opts->rounds < 0) return fail(PF_ERR_ARG, "rounds must be >= 0");
+  if (opts->resume && !m->qp_started) return fail(PF_ERR_ARG, "resume without a previous damage solve on this handle");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = upload_params(m, p, nullptr, s)) != PF_OK) return st;
+  m->qp_started = true;
   return damage_cg(m, CG_QP, H, d_prev, d, active_guess, active_out, opts, stats, s);
 }

@@ -561,15 +561,14 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
 
   // workspaces
   const size_t nb = size_t(m->n_nodes) * w;
-  void** vecs[] = {&m->dw.b, &m->dw.dinv, &m->dw.r, &m->dw.z, &m->dw.p0, &m->dw.p1, &m->dw.q,
-                   &m->dw.lam, &m->dw.t0, &m->dw.t1};
+  void** vecs[] = {&m->dw.b,  &m->dw.dinv, &m->dw.r0, &m->dw.r1,  &m->dw.w0,  &m->dw.w1,
+                   &m->dw.s0, &m->dw.s1,   &m->dw.p,  &m->dw.xw0, &m->dw.xw1, &m->dw.lam};
   for (void** v : vecs)
     if ((st = dev_alloc(m, nb, v)) != PF_OK) { free_all(m); delete m; return st; }
   void* tmpp;
   if ((st = dev_alloc(m, size_t(m->n_elems) * w, &m->dw.hbar)) != PF_OK) { free_all(m); delete m; return st; }
-  if ((st = dev_alloc(m, size_t(m->n_nodes) * w, &m->dw.xw)) != PF_OK) { free_all(m); delete m; return st; }
   if ((st = dev_alloc(m, size_t(m->n_te) * w, &m->dw.mte)) != PF_OK) { free_all(m); delete m; return st; }
-  if ((st = dev_alloc(m, size_t(m->n_nodes), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
+  if ((st = dev_alloc(m, 2 * size_t(m->n_nodes), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
   m->dw.wset = static_cast<uint8_t*>(tmpp);
   if ((st = dev_alloc(m, size_t(m->n_tiles) * 8 * sizeof(double), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
   m->dw.part = static_cast<double*>(tmpp);
@@ -596,14 +595,15 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     hipError_t e = hipMemcpy(m->dw.ctl, c.data(), sizeof(Ctl) * n_instances, hipMemcpyHostToDevice);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipMemcpy"); }
   }
-  // LDS needs: explicit = 3 node values + 6 corner values; damage = 1 node value + 7 element values
+  // LDS needs: explicit = 3 node values + 6 corner values; damage = 1 node value,
+  // then per element the larger of 3 FP64 corner values and 4 values of width w
   int32_t max_loc = 0, max_te = 0;
   for (const TileRec& t : m->tiles_h) {
     max_loc = std::max(max_loc, t.n_own + t.n_halo);
     max_te = std::max(max_te, t.n_telem);
   }
   m->max_lds_explicit = int32_t((3 * size_t(max_loc) + 6 * size_t(max_te)) * w + 64);
-  m->max_lds_damage = int32_t((size_t(max_loc) + 7 * size_t(max_te)) * w + 64);
+  m->max_lds_damage = int32_t(((size_t(max_loc) * w + 7) & ~size_t(7)) + size_t(max_te) * std::max<size_t>(24, 4 * w) + 64);
   int dev = 0, lds_limit = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_limit <= 0)

@@ -50,25 +50,25 @@ struct InstP {
 // CG control block of one instance, in device memory.  Fields are read by
 // every block at kernel start and written only by the instance's last block.
 struct Ctl {
-  int32_t mode;       // 0 restart pending, 1 iterate, 2 done
+  int32_t mode;       // MODE_*
   int32_t setup;      // 1 on the first restart of a solve (assemble b and the diagonal)
   int32_t release;    // the pending restart may release nodes held at the bound
   int32_t hit;        // the current step is cut by a bound
   int32_t iters, restarts, flags, nact;
-  int32_t pbuf;       // which search-direction buffer holds the current p
+  int32_t pbuf;       // which half of the vector pairs (x, r, A z, A p) is current
   int32_t ntiles;     // tiles of this instance
   int32_t tile0;      // first tile of this instance
   int32_t flavor;     // 0 active-set updates between CG runs, 1 monotone projected CG (fallback)
   int32_t nnodes;     // nodes of this instance
   int32_t inner;      // CG iterations since the last restart or check
-  int32_t pad1;
+  int32_t wbuf;       // which half of the held-set pair is current
   int32_t outer;      // active-set updates so far
   double rz, alpha, beta, amax, resid, pq;
   double ref;         // scale of the stopping test (1 for the damage QP, max |b_i|/A_ii for linear solves)
   double pad2;
 };
 
-enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2, MODE_CHECK = 3 };
+enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2, MODE_CHECK = 3, MODE_FIRST = 4 };
 
 // Device view of a mesh handle.
 struct DevMesh {
@@ -89,11 +89,15 @@ struct DevMesh {
 
 // Device workspaces of the damage solve and of the adjoint.
 struct DevWork {
-  void* b; void* dinv; void* r; void* z; void* p0; void* p1; void* q;
-  uint8_t* wset;
-  void* lam; void* t0; void* t1;     // adjoint scratch vectors
+  void* b; void* dinv;               // [n_nodes] CG load vector and Jacobi diagonal inverse
+  void* r0; void* r1;                // [n_nodes] residual pair
+  void* w0; void* w1;                // [n_nodes] A z pair
+  void* s0; void* s1;                // [n_nodes] A p pair
+  void* p;                           // [n_nodes] search direction
+  void* xw0; void* xw1;              // [n_nodes] iterate pair of the damage solve
+  uint8_t* wset;                     // [2][n_nodes] held-set pair
+  void* lam;                         // [n_nodes] adjoint multiplier (warm start of the next adjoint solve)
   void* hbar;                        // [n_elems] adjoint of H_{n+1} (adjoint step scratch)
-  void* xw;                          // [n_nodes] damage iterate of the solve
   void* mte;                         // [n_te] per-solve mass coefficient (c0 + cH H_e) A_e / 12 of each tile element
   double* part;                      // [n_tiles][8] block partials
   Ctl* ctl;                          // [n_inst]
@@ -125,6 +129,8 @@ struct pf_mesh_s {
   // host mirror of the current per-instance parameters (bytes of InstP<T>[n_inst])
   std::vector<unsigned char> instp_host;
   std::vector<double> dt_cache;      // dt of the last explicit step (the damage solve reuses it)
+  int32_t last_rounds[2] = {0, 0};   // CG rounds the last solve of each kind needed (sets the first poll)
+  bool qp_started = false;           // a damage solve has been enqueued (resume is allowed)
   pf::Ctl* ctl_pinned = nullptr;     // pinned host copy of the control blocks
   bool timing = false;
   pf::Timer timers[5];

@@ -179,9 +179,12 @@ class CgConfig:
     check_every: int = 8
     start: int = 1          # damage solve: 1 = extrapolate from the two previous damage fields
     monotone: int = 0       # damage solve: 1 = monotone projected CG from the start
+    rounds: int = 0         # check_every = 0: CG rounds to enqueue (0 = max_iter)
+    resume: int = 0         # damage solve: 1 = continue the handle's previous solve
 
     def opts(self) -> L.CgOpts:
-        return L.CgOpts(self.tol, self.max_iter, self.check_every, self.start, self.monotone)
+        return L.CgOpts(self.tol, self.max_iter, self.check_every, self.start, self.monotone, self.rounds,
+                        self.resume)
 
 
 def default_tol(dtype: str) -> float:
@@ -191,12 +194,15 @@ def default_tol(dtype: str) -> float:
 class Simulator:
     """Staggered explicit phase-field simulation of one or more instances on one GPU."""
 
-    def __init__(self, problems, dtype: str | None = None, tile_nodes: int = 0, cg: CgConfig | None = None,
+    def __init__(self, problems, dtype: str | None = None, tile_nodes: int | str = 0, cg: CgConfig | None = None,
                  dt: list[float] | None = None, mesh: Mesh | None = None, cg_adj: CgConfig | None = None):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
         self.dtype_code = dtype or self.problems[0].dtype
+        if mesh is None and tile_nodes == "auto":
+            from .tune import tune_tiles
+            tile_nodes = tune_tiles(self.problems, self.dtype_code)["best"]
         self.mesh = mesh or Mesh(self.problems, self.dtype_code, tile_nodes)
         n = len(self.problems)
         self.params = (L.Params * n)(*[params_of(p) for p in self.problems])
@@ -245,9 +251,10 @@ class Simulator:
                _ptr(f_ext), _stream())
 
     def damage(self, H: torch.Tensor, d_prev: torch.Tensor, d_out: torch.Tensor,
-               active: torch.Tensor | None = None, guess: torch.Tensor | None = None) -> None:
+               active: torch.Tensor | None = None, guess: torch.Tensor | None = None,
+               cg: CgConfig | None = None) -> None:
         """Damage update; `guess` seeds the held set (normally the previous step's flags)."""
-        o = self.cg.opts()
+        o = (cg or self.cg).opts()
         L.call("pf_damage_solve", self.mesh.handle, self.params, H.data_ptr(), d_prev.data_ptr(), d_out.data_ptr(),
                _ptr(guess), _ptr(active), C.byref(o), self.stats.data_ptr(), _stream())
 
@@ -285,3 +292,67 @@ class Simulator:
         n = C.c_int64()
         L.call("pf_timer_read", self.mesh.handle, family, C.byref(ms), C.byref(n))
         return ms.value, n.value
+
+
+class GraphStepper:
+    """Staggered steps of a Simulator replayed from HIP graphs.
+
+    For each direction of the simulator's ping-pong state pair, one graph holds
+    the explicit step and the first `rounds` rounds of the damage solve, and a
+    second graph `more` further rounds (resume).  A step replays the first
+    graph, reads the per-instance CG statistics once, and replays the second
+    until every instance has finished, so results equal Simulator.step bit for
+    bit.  The material parameters and time steps are those of the capture;
+    build a new stepper after changing them.
+    """
+
+    def __init__(self, sim: Simulator, rounds: int = 24, more: int = 8):
+        self.sim = sim
+        base = sim.cg
+        first = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, rounds, 0)
+        cont = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, more, 1)
+        self.max_iter = base.max_iter
+        # one eager step so the device holds this simulator's parameters (a
+        # captured call must not upload anything)
+        sim.step()
+        torch.cuda.synchronize()
+        self._params = bytes(sim.params)
+        self._dt = list(sim.dt)
+        self.states = (sim.state, sim._next)
+        self.actives = (sim.active, sim._active_next)
+        self.graphs = []
+        for k in (0, 1):
+            s_in, s_out = self.states[k], self.states[1 - k]
+            a_in, a_out = self.actives[k], self.actives[1 - k]
+            g1, g2 = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g1):
+                sim.explicit(s_in, s_out)
+                sim.damage(s_out.H, s_in.d, s_out.d, a_out, a_in, cg=first)
+            with torch.cuda.graph(g2):
+                sim.damage(s_out.H, s_in.d, s_out.d, a_out, a_in, cg=cont)
+            self.graphs.append((g1, g2))
+        self.parity = 0
+        self.continuations = 0
+
+    def step(self, n: int = 1) -> State:
+        sim = self.sim
+        if bytes(sim.params) != self._params or list(sim.dt) != self._dt:
+            raise RuntimeError("parameters changed since the graphs were captured")
+        for _ in range(n):
+            g1, g2 = self.graphs[self.parity]
+            g1.replay()
+            while True:
+                st = sim.stats.cpu().numpy().view(np.int32).reshape(-1, 6)
+                if not np.any(st[:, 3] & L.PF_FLAG_NONFINITE) and not np.any(st[:, 3] & L.PF_FLAG_NOT_CONVERGED):
+                    break
+                if np.any(st[:, 3] & L.PF_FLAG_NONFINITE):
+                    raise L.PfError(L.PF_ERR_NONFINITE, "GraphStepper.step", "non-finite value in the damage CG")
+                if np.any(st[:, 0] >= self.max_iter):
+                    raise L.PfError(L.PF_ERR_NOT_CONVERGED, "GraphStepper.step", "damage CG reached max_iter")
+                g2.replay()
+                self.continuations += 1
+            self.parity ^= 1
+            sim.state, sim._next = self.states[self.parity], self.states[1 - self.parity]
+            sim.active, sim._active_next = self.actives[self.parity], self.actives[1 - self.parity]
+            sim.steps_done += 1
+        return sim.state

@@ -36,12 +36,15 @@ def test_struct_layouts_match_header(tmp_path):
         "pf_params_t": (L.Params, ["E", "nu", "rho", "Gc", "l0", "eta", "gamma_star", "model", "split", "plane",
                                    "bounds"]),
         "pf_state_t": (L.StatePtrs, ["ux", "uy", "vx", "vy", "ax", "ay", "d", "H"]),
-        "pf_cg_opts_t": (L.CgOpts, ["tol", "max_iter", "check_every", "start", "monotone"]),
+        "pf_cg_opts_t": (L.CgOpts, ["tol", "max_iter", "check_every", "start", "monotone", "rounds", "resume"]),
         "pf_cg_stats_t": (L.CgStats, ["iters", "restarts", "n_active", "flags", "resid"]),
         "pf_instance_info_t": (L.InstanceInfo, ["node_offset", "n_nodes", "elem_offset", "n_elems", "tile_offset",
                                                 "n_tiles", "h_min", "area"]),
         "pf_mesh_totals_t": (L.Totals, ["n_instances", "n_nodes", "n_elems", "n_tiles", "dtype", "max_tile_nodes",
                                         "max_tile_elems", "tile_elems_total", "device_bytes"]),
+        "pf_tune_opts_t": (L.TuneOpts, ["n_candidates", "tile_nodes", "reps", "cg_rounds_per_step"]),
+        "pf_tune_result_t": (L.TuneResult, ["best", "n_tried", "tile_nodes", "status", "explicit_us", "cg_round_us",
+                                            "score_us"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for t, (_, fields) in checks.items():
@@ -99,6 +102,17 @@ def test_argument_errors():
     assert lib.pf_explicit_step(None, None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_damage_solve(None, None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_step_backward(None, None, None, None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG
+    assert lib.pf_tune_tiles(None, 1, 0, None, None, None, None) == L.PF_ERR_ARG
+    res = L.TuneResult()
+    descs = (L.MeshDesc * 1)()
+    params = (L.Params * 1)()
+    bad = L.TuneOpts()
+    bad.n_candidates = 9
+    assert lib.pf_tune_tiles(descs, 1, 0, params, C.byref(bad), C.byref(res), None) == L.PF_ERR_ARG
+    bad.n_candidates = 1
+    bad.tile_nodes[0] = 32
+    assert lib.pf_tune_tiles(descs, 1, 0, params, C.byref(bad), C.byref(res), None) == L.PF_ERR_ARG
+    assert "tile_nodes" in lib.pf_last_error().decode()
     assert lib.pf_mesh_destroy(None) == L.PF_OK
     tot = L.Totals()
     assert lib.pf_mesh_totals(None, C.byref(tot)) == L.PF_ERR_ARG
