@@ -64,8 +64,10 @@ constexpr double kRelease = 2.0;       // held nodes are released when their sca
 // held-set states; HELD_FIXED: d_prev = 1, the node cannot move
 enum { HELD_NONE = 0, HELD_LOWER = 1, HELD_UPPER = 2, HELD_FIXED = 3 };
 
-// partial sums of one tile
+// partial sums of one tile, and how each combines (2 bits each: 0 sum, 1 min, 2 max)
 enum { PT_DELTA = 0, PT_AMIN = 1, PT_GAMMA = 2, PT_CF = 3, PT_CA = 4, PT_NA = 5, PT_RB = 6, PT_CH = 7 };
+constexpr uint32_t kPartOps = (0u << 0) | (1u << 2) | (0u << 4) | (2u << 6) | (2u << 8) | (0u << 10) | (2u << 12) |
+                              (0u << 14);
 
 template <typename T>
 struct DmgArgs {
@@ -124,7 +126,7 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
-  __shared__ double red[kWaves];
+  __shared__ double red[8 * kWaves];
   const TileRec t = a.dm.tiles[blockIdx.x];
   const Ctl* c = a.ctl + t.inst;
   const int mode = c->mode;
@@ -368,55 +370,38 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       }
     }
   }
-  del = block_sum(del, red);
-  amin = block_min(amin, red);
-  gam = block_sum(gam, red);
-  cf = block_max(cf, red);
-  ca = block_max(ca, red);
-  na = block_sum(na, red);
-  rb = block_max(rb, red);
-  ch = block_sum(ch, red);
+  double v[8] = {del, amin, gam, cf, ca, na, rb, ch};   // in PT_* order
+  block_reduce<8, kPartOps>(v, red);
   if (tid == 0) {
     double* pp = a.part + 8 * blockIdx.x;
-    pp[PT_DELTA] = del;
-    pp[PT_AMIN] = amin;
-    pp[PT_GAMMA] = gam;
-    pp[PT_CF] = cf;
-    pp[PT_CA] = ca;
-    pp[PT_NA] = na;
-    pp[PT_RB] = rb;
-    pp[PT_CH] = ch;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pp[k] = v[k];
   }
 }
 
 // One workgroup per instance: combine the tiles' partials and advance the state.
 __global__ __launch_bounds__(kBlock) void k_dmg_red(Ctl* ctl, const double* part, const int* bounds, int kind,
                                                     double tol, int max_iter) {
-  __shared__ double red[kWaves];
+  __shared__ double red[8 * kWaves];
   Ctl* c = ctl + blockIdx.x;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
-  double sdel = 0.0, samin = INFINITY, sgam = 0.0, scf = 0.0, sca = -INFINITY, sna = 0.0, srb = 0.0, sch = 0.0;
+  double v[8] = {0.0, INFINITY, 0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < c->ntiles; k += kBlock) {
     const double* pp = part + 8 * (c->tile0 + k);
-    sdel += pp[PT_DELTA];
-    samin = fmin(samin, pp[PT_AMIN]);
-    sgam += pp[PT_GAMMA];
-    scf = fmax(scf, pp[PT_CF]);
-    sca = fmax(sca, pp[PT_CA]);
-    sna += pp[PT_NA];
-    srb = fmax(srb, pp[PT_RB]);
-    sch += pp[PT_CH];
+    v[PT_DELTA] += pp[PT_DELTA];
+    v[PT_AMIN] = fmin(v[PT_AMIN], pp[PT_AMIN]);
+    v[PT_GAMMA] += pp[PT_GAMMA];
+    v[PT_CF] = fmax(v[PT_CF], pp[PT_CF]);
+    v[PT_CA] = fmax(v[PT_CA], pp[PT_CA]);
+    v[PT_NA] += pp[PT_NA];
+    v[PT_RB] = fmax(v[PT_RB], pp[PT_RB]);
+    v[PT_CH] += pp[PT_CH];
   }
-  sdel = block_sum(sdel, red);
-  samin = block_min(samin, red);
-  sgam = block_sum(sgam, red);
-  scf = block_max(scf, red);
-  sca = block_max(sca, red);
-  sna = block_sum(sna, red);
-  srb = block_max(srb, red);
-  sch = block_sum(sch, red);
+  block_reduce<8, kPartOps>(v, red);
   if (threadIdx.x != 0) return;
+  const double sdel = v[PT_DELTA], samin = v[PT_AMIN], sgam = v[PT_GAMMA], scf = v[PT_CF], sca = v[PT_CA];
+  const double sna = v[PT_NA], srb = v[PT_RB], sch = v[PT_CH];
   const bool qp = (kind == CG_QP);
   const bool projected = qp && (bounds[blockIdx.x] == PF_BOUNDS_PROJECTED);
   const bool monotone = projected && (c->flavor != 0);

@@ -89,4 +89,35 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
   return s;
 }
 
+// Several block-wide reductions at once, with one barrier: every wave
+// reduces each value by shuffles, lane 0 of each wave stores its results, and
+// every thread combines the waves in a fixed order.  OPS holds two bits per
+// value: 0 sum, 1 min, 2 max.  `sh` holds K * kWaves doubles and must not be
+// in use by another reduction of the same block.
+template <int K, uint32_t OPS>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* sh) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t op = (OPS >> (2 * k)) & 3u;
+    v[k] = op == 0 ? wave_sum(v[k]) : (op == 1 ? wave_min(v[k]) : wave_max(v[k]));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * kWaves + w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t op = (OPS >> (2 * k)) & 3u;
+    double s = sh[k * kWaves];
+#pragma unroll
+    for (int j = 1; j < kWaves; ++j) {
+      const double y = sh[k * kWaves + j];
+      s = op == 0 ? s + y : (op == 1 ? fmin(s, y) : fmax(s, y));
+    }
+    v[k] = s;
+  }
+}
+
 }  // namespace pf
