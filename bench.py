@@ -116,6 +116,29 @@ def explicit_only(res, steps: int) -> dict:
                     "back-to-back launches incl. launch gaps"}
 
 
+def graph_steps(steps: int, tile_nodes) -> dict:
+    """The same staggered steps replayed from HIP graphs (GraphStepper)."""
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import GraphStepper, Simulator
+    p = w.config1()
+    sim = Simulator(p, dtype="f32", tile_nodes=tile_nodes)
+    sim.step(20)
+    gs = GraphStepper(sim, rounds=24, more=8)
+    gs.step(5)
+    gpu_sync()
+    c0 = gs.continuations
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    gs.step(steps)
+    ev1.record()
+    gpu_sync()
+    ms = ev0.elapsed_time(ev1) / steps
+    return {"elem_steps_per_s": round(sim.mesh.n_elems / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+            "continuations_per_step": round((gs.continuations - c0) / steps, 3),
+            "note": "explicit step + first 24 CG rounds in one graph, 8-round continuation graphs as needed"}
+
+
 def roofline(res, w: int) -> dict:
     ne = res["ne"]
     fam = res["fam"]
@@ -258,6 +281,7 @@ def main():
                    "n_elems": res["ne"], "n_nodes": res["sim"].mesh.n_nodes, "precision": "fp32 kernels, fp64 CG reductions"},
         "roofline": roofline(res, 4),
         "explicit_step": explicit_only(res, args.steps),
+        "graph_replay": graph_steps(args.steps, args.tile_nodes),
         "cg_iters_per_solve": {"mean": round(sum(iters) / len(iters), 2), "max": max(iters)},
     }
     if not args.no_extras:

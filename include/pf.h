@@ -111,8 +111,8 @@ typedef struct {
 typedef struct {
     double tol;              /* stop when max_i |r_i|/A_ii <= tol on free nodes and
                                 no node held at a bound has a scaled residual
-                                pointing inward by more than 2 tol (held nodes
-                                are released beyond that margin) */
+                                r_i/A_ii pointing inward by more than tol/4
+                                (held nodes beyond that are released) */
     int32_t max_iter;        /* matrix-vector products per solve, >= 1 */
     int32_t check_every;     /* > 0: synchronise the stream to stop early: first
                                 after as many CG rounds as the handle's previous

@@ -13,11 +13,12 @@
 // guess (normally the previous step's flags).  After each converged CG run
 // a check pass recomputes the true residual r = b - Ax, moves free nodes that
 // left [d_prev, 1] onto the bound they crossed, and releases held nodes whose
-// scaled residual r_i/A_ii points into the interior by more than 2 tol; the
+// scaled residual r_i/A_ii points into the interior by more than tol/4; the
 // solve ends when a check changes nothing and the free residual passes.
-// (Releasing at tol itself lets nodes whose residual sits just above tol
-// leave one ring at a time, a check each, where the solution varies on the
-// scale of tol; the margin ends that.)
+// (With a release threshold near tol, where the solution's tail varies on the
+// scale of tol, each release pushes the next ring of held nodes just over the
+// threshold and the held set shrinks one ring per check; well below tol the
+// whole tail is released at once.)
 // Each check is one primal-dual active-set update; if eight updates have not
 // settled the set, the solve switches to a monotone projected CG: steps are
 // cut at the first bound and followed by a projected Jacobi-gradient step of
@@ -58,7 +59,7 @@ namespace pf {
 
 constexpr int kSwitchAfter = 8;        // active-set updates before the monotone fallback
 constexpr double kExpandStep = 0.25;   // projected-gradient step of the fallback
-constexpr double kRelease = 2.0;       // held nodes are released when their scaled residual
+constexpr double kRelease = 0.25;      // held nodes are released when their scaled residual
                                        // points inward by more than kRelease * tol
 
 // held-set states; HELD_FIXED: d_prev = 1, the node cannot move

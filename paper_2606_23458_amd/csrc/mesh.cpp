@@ -177,7 +177,8 @@ void timer_begin(pf_mesh_s* m, int family, hipStream_t s) {
     }
     if (t.ev.empty()) {
       t.ev.resize(2 * 4096);
-      for (auto& e : t.ev) (void)hipEventCreate(&e);
+      // no system-scope fence: the events only time kernels on this device
+      for (auto& e : t.ev) (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     }
   }
   (void)hipEventRecord(t.ev[2 * t.used], s);
