@@ -22,7 +22,8 @@ namespace pf {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* __restrict__ act,
                                                      const T* __restrict__ dbar, T* b, uint8_t* W, T* lam) {
-  const TileRec t = dm.tiles[blockIdx.x];
+  const int tile = tile_of_block(dm.n_tiles);
+  const TileRec t = dm.tiles[tile];
   for (int i = threadIdx.x; i < t.n_own; i += kBlock) {
     const int g = t.node_begin + i;
     const uint8_t a = act[g];
@@ -40,7 +41,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
                                                        const T* __restrict__ dbar, const T* __restrict__ hbar_in,
                                                        const uint8_t* __restrict__ W, T* hbar, T* dprev_bar) {
   __shared__ double red[kWaves];
-  const TileRec t = dm.tiles[blockIdx.x];
+  const int tile = tile_of_block(dm.n_tiles);
+  const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
@@ -95,15 +97,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
     dprev_bar[g] = (W[g] == 1) ? dbar[g] - qi : T(0);
   }
   gsum = block_sum(gsum, red);
-  if (tid == 0) part[8 * blockIdx.x + 7] = gsum;
+  if (tid == 0) part[size_t(7) * dm.n_tiles + tile] = gsum;   // value-major partials, slot 7
 }
 
 // One workgroup per instance: dGc += the instance's tile partials, fixed order.
-__global__ __launch_bounds__(kBlock) void k_adj_reduce(const Ctl* ctl, const double* part, double* dGc) {
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(const Ctl* ctl, const double* part, int n_tiles, double* dGc) {
   __shared__ double red[kWaves];
   const Ctl* c = ctl + blockIdx.x;
   double s = 0.0;
-  for (int k = threadIdx.x; k < c->ntiles; k += kBlock) s += part[8 * (c->tile0 + k) + 7];
+  const double* p7 = part + size_t(7) * n_tiles + c->tile0;
+  for (int k = threadIdx.x; k < c->ntiles; k += kBlock) s += p7[k];
   s = block_sum(s, red);
   if (threadIdx.x == 0) dGc[blockIdx.x] += s;
 }
@@ -112,7 +115,8 @@ template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> sn,
                                                          StateIn<T> snp1, StateIn<T> adj1,
                                                          const T* __restrict__ hbar, StateOut<T> adj0) {
-  const TileRec t = dm.tiles[blockIdx.x];
+  const int tile = tile_of_block(dm.n_tiles);
+  const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
@@ -227,7 +231,7 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
                      static_cast<const T*>(s_np1->d), static_cast<const T*>(s_np1->H),
                      static_cast<const T*>(adj1->d), static_cast<const T*>(adj1->H), m->dw.wset,
                      static_cast<T*>(m->dw.hbar), static_cast<T*>(adj0->d));
-  hipLaunchKernelGGL(k_adj_reduce, dim3(m->n_inst), block, 0, s, m->dw.ctl, m->dw.part, dGc);
+  hipLaunchKernelGGL(k_adj_reduce, dim3(m->n_inst), block, 0, s, m->dw.ctl, m->dw.part, m->n_tiles, dGc);
   const StateIn<T> sn = state_in<T>(s_n), sn1 = state_in<T>(s_np1), a1 = state_in<T>(adj1);
   const StateOut<T> a0 = state_out<T>(adj0);
   const T* hb = static_cast<const T*>(m->dw.hbar);

@@ -125,10 +125,11 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
   return v < lo ? lo : (v > T(1) ? T(1) : v);
 }
 
-template <typename T>
+template <typename T, int NPT>
 __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[8 * kWaves];
-  const TileRec t = a.dm.tiles[blockIdx.x];
+  const int tile = tile_of_block(a.dm.n_tiles);
+  const TileRec t = a.dm.tiles[tile];
   const Ctl* c = a.ctl + t.inst;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
@@ -163,13 +164,14 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   T* sv = reinterpret_cast<T*>(smem);          // [nloc] the vector the pass multiplies by A
   // after sv (8-byte aligned): iteration passes keep the element corner values
   // of A^e z^e in T; restart and check passes keep them in FP64 (the true
-  // residual is then accurate to the rounding of x, not of an FP32 matvec);
-  // the set-up sweep first uses the same space for diagonal corners and loads
+  // residual is then accurate to the rounding of x, not of an FP32 matvec) a
+  // chunk of elements at a time; the set-up sweep uses the same space for
+  // diagonal corners and loads
   unsigned char* rest = smem + ((size_t(nloc) * sizeof(T) + 7) & ~size_t(7));
   T* qc = reinterpret_cast<T*>(rest);          // [3 n_telem] (first, iterate)
-  double* qd = reinterpret_cast<double*>(rest); // [3 n_telem] (restart, check)
-  T* dc = reinterpret_cast<T*>(rest);          // [3 n_telem] diagonal corners (set-up)
-  T* bc = dc + 3 * t.n_telem;                  // [n_telem]   load per corner (set-up, QP)
+  double* qd = reinterpret_cast<double*>(rest); // [3 chunk]   (restart, check)
+  T* dc = reinterpret_cast<T*>(rest);          // [3 chunk]   diagonal corners (set-up)
+  T* bc = dc;                                  // [chunk] from offset 3 chunk: load per corner (set-up)
   const int tid = threadIdx.x;
 
   // ---- phase 1: the vector to multiply, on owned and halo nodes -------------
@@ -234,79 +236,119 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   }
 
   // ---- set-up: load vector, Jacobi diagonal, per-solve mass coefficients ----
+  // The space after sv holds the corner values of one pass; restart and check
+  // passes (FP64 values) and the set-up sweep work through the tile's
+  // elements in chunks that fit it, each owned node adding the corners of a
+  // chunk in its fixed corner order.
   const T* __restrict__ geo = static_cast<const T*>(a.dm.geo);
   const size_t nte = size_t(a.dm.n_te);
   if (setup) {
-    for (int e = tid; e < t.n_telem; e += kBlock) {
-      const int te = t.telem_begin + e;
-      const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-      const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-      const T kA = P.kap * A;
-      const T He = a.H[a.dm.te_gid[te]];
-      const T mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
-      a.mte[te] = mA;
-      dc[3 * e + 0] = kA * (g0x * g0x + g0y * g0y) + T(2) * mA;
-      dc[3 * e + 1] = kA * (g1x * g1x + g1y * g1y) + T(2) * mA;
-      dc[3 * e + 2] = kA * (g2x * g2x + g2y * g2y) + T(2) * mA;
-      bc[e] = qp ? (P.b0 + P.bH * He) * A * T(1.0 / 3.0) : T(0);
-    }
-    __syncthreads();
-    for (int i = tid; i < t.n_own; i += kBlock) {
-      const int g = t.node_begin + i;
-      const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
-      T di = T(0), bi = T(0);
-      for (int j = j0; j < j1; ++j) {
-        const int cc = a.dm.lcorner[j];
-        di += dc[cc];
-        bi += bc[cc / 3];
+    T dacc[NPT], bacc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) dacc[r] = T(0), bacc[r] = T(0);
+    // two chunks: 4 values of width w per element in two halves fit the 3
+    // values per element of an iteration pass (chunk sizes depend only on the
+    // tile, so the sums are the same in a batched and a single-instance handle)
+    const int chs = (t.n_telem + 1) / 2;
+    for (int e0 = 0; e0 < t.n_telem; e0 += chs) {
+      const int e1 = min(e0 + chs, t.n_telem);
+      __syncthreads();
+      for (int e = e0 + tid; e < e1; e += kBlock) {
+        const int te = t.telem_begin + e;
+        const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+        const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+        const T kA = P.kap * A;
+        const T He = a.H[a.dm.te_gid[te]];
+        const T mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
+        a.mte[te] = mA;
+        const int l = e - e0;
+        dc[3 * l + 0] = kA * (g0x * g0x + g0y * g0y) + T(2) * mA;
+        dc[3 * l + 1] = kA * (g1x * g1x + g1y * g1y) + T(2) * mA;
+        dc[3 * l + 2] = kA * (g2x * g2x + g2y * g2y) + T(2) * mA;
+        bc[3 * chs + l] = qp ? (P.b0 + P.bH * He) * A * T(1.0 / 3.0) : T(0);
       }
-      if (qp) a.b[g] = bi;
-      a.dinv[g] = T(1) / di;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NPT; ++r) {
+        const int i = tid + r * kBlock;
+        if (i < t.n_own) {
+          const int g = t.node_begin + i;
+          const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+          for (int j = j0; j < j1; ++j) {
+            const int cc = a.dm.lcorner[j];
+            const int e = cc / 3;
+            if (e >= e0 && e < e1) {
+              dacc[r] += dc[cc - 3 * e0];
+              bacc[r] += bc[3 * chs + e - e0];
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int i = tid + r * kBlock;
+      if (i < t.n_own) {
+        const int g = t.node_begin + i;
+        if (qp) a.b[g] = bacc[r];
+        a.dinv[g] = T(1) / dacc[r];
+      }
     }
   }
-  __syncthreads();
 
-  // ---- phase 2: element corner values of A^e v^e ----------------------------
-  for (int e = tid; e < t.n_telem; e += kBlock) {
-    const int te = t.telem_begin + e;
-    const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
-    const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-    const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-    const T kA = P.kap * A;
-    const T mA = a.mte[te];
-    if (xpass) {
-      const double s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
-      const double gpx = double(g0x) * s0 + double(g1x) * s1 + double(g2x) * s2;
-      const double gpy = double(g0y) * s0 + double(g1y) * s1 + double(g2y) * s2;
-      const double ss = s0 + s1 + s2;
-      const double k = kA, mm = mA;
-      qd[3 * e + 0] = k * (double(g0x) * gpx + double(g0y) * gpy) + mm * (s0 + ss);
-      qd[3 * e + 1] = k * (double(g1x) * gpx + double(g1y) * gpy) + mm * (s1 + ss);
-      qd[3 * e + 2] = k * (double(g2x) * gpx + double(g2y) * gpy) + mm * (s2 + ss);
-    } else {
-      const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
-      const T gpx = g0x * s0 + g1x * s1 + g2x * s2;
-      const T gpy = g0y * s0 + g1y * s1 + g2y * s2;
-      const T ss = s0 + s1 + s2;
-      qc[3 * e + 0] = kA * (g0x * gpx + g0y * gpy) + mA * (s0 + ss);
-      qc[3 * e + 1] = kA * (g1x * gpx + g1y * gpy) + mA * (s1 + ss);
-      qc[3 * e + 2] = kA * (g2x * gpx + g2y * gpy) + mA * (s2 + ss);
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 3: gather per owned node, then the pass's node work -----------
   // partials: gamma = r'z, delta = z'Az, max free |r|/A_ii, max held "wants
   // to leave" r/A_ii, held count, max |b|/A_ii (linear set-up), changes
   double gam = 0.0, del = 0.0, cf = 0.0, ca = -INFINITY, na = 0.0, rb = 0.0;
   if (xpass) {
-    for (int i = tid; i < t.n_own; i += kBlock) {
+    // ---- restart / check: true residual b - A x with FP64 corner values ----
+    double qacc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) qacc[r] = 0.0;
+    // FP64 corner values: two chunks in FP32 (3 doubles per element in the
+    // space of 6 floats), one in FP64
+    const int chx = sizeof(T) == 4 ? (t.n_telem + 1) / 2 : t.n_telem;
+    for (int e0 = 0; e0 < t.n_telem; e0 += chx) {
+      const int e1 = min(e0 + chx, t.n_telem);
+      __syncthreads();
+      for (int e = e0 + tid; e < e1; e += kBlock) {
+        const int te = t.telem_begin + e;
+        const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
+        const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+        const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+        const T kA = P.kap * A;
+        const T mA = a.mte[te];
+        const double s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
+        const double gpx = double(g0x) * s0 + double(g1x) * s1 + double(g2x) * s2;
+        const double gpy = double(g0y) * s0 + double(g1y) * s1 + double(g2y) * s2;
+        const double ss = s0 + s1 + s2;
+        const double k = kA, mm = mA;
+        const int l = e - e0;
+        qd[3 * l + 0] = k * (double(g0x) * gpx + double(g0y) * gpy) + mm * (s0 + ss);
+        qd[3 * l + 1] = k * (double(g1x) * gpx + double(g1y) * gpy) + mm * (s1 + ss);
+        qd[3 * l + 2] = k * (double(g2x) * gpx + double(g2y) * gpy) + mm * (s2 + ss);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NPT; ++r) {
+        const int i = tid + r * kBlock;
+        if (i < t.n_own) {
+          const int g = t.node_begin + i;
+          const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+          for (int j = j0; j < j1; ++j) {
+            const int cc = a.dm.lcorner[j];
+            const int e = cc / 3;
+            if (e >= e0 && e < e1) qacc[r] += qd[cc - 3 * e0];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int i = tid + r * kBlock;
+      if (i >= t.n_own) continue;
       const int g = t.node_begin + i;
-      const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
-      double qi = 0.0;
-      for (int j = j0; j < j1; ++j) qi += qd[a.dm.lcorner[j]];
       const T bi = a.b[g];
-      const T ri = T(double(bi) - qi);
+      const T ri = T(double(bi) - qacc[r]);
       const T di = a.dinv[g];
       const double sr = double(ri) * double(di);
       T xv = sv[i];
@@ -350,6 +392,24 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       }
     }
   } else {
+    // ---- first / iterate: corner values of A^e z^e in T ----------------------
+    __syncthreads();
+    for (int e = tid; e < t.n_telem; e += kBlock) {
+      const int te = t.telem_begin + e;
+      const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
+      const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+      const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+      const T kA = P.kap * A;
+      const T mA = a.mte[te];
+      const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
+      const T gpx = g0x * s0 + g1x * s1 + g2x * s2;
+      const T gpy = g0y * s0 + g1y * s1 + g2y * s2;
+      const T ss = s0 + s1 + s2;
+      qc[3 * e + 0] = kA * (g0x * gpx + g0y * gpy) + mA * (s0 + ss);
+      qc[3 * e + 1] = kA * (g1x * gpx + g1y * gpy) + mA * (s1 + ss);
+      qc[3 * e + 2] = kA * (g2x * gpx + g2y * gpy) + mA * (s2 + ss);
+    }
+    __syncthreads();
     T* wn = iter ? wn_ : (cur1 ? a.w1 : a.w0);
     const T* rz = iter ? rn_ : rc;
     for (int i = tid; i < t.n_own; i += kBlock) {
@@ -372,34 +432,36 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     }
   }
   double v[8] = {del, amin, gam, cf, ca, na, rb, ch};   // in PT_* order
-  block_reduce<8, kPartOps>(v, red);
+  block_reduce_to0<8, kPartOps>(v, red);
+  // partials are stored value-major, [8][n_tiles], so the reduction reads them coalesced
   if (tid == 0) {
-    double* pp = a.part + 8 * blockIdx.x;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) pp[k] = v[k];
+    for (int k = 0; k < 8; ++k) a.part[size_t(k) * a.dm.n_tiles + tile] = v[k];
   }
 }
 
 // One workgroup per instance: combine the tiles' partials and advance the state.
-__global__ __launch_bounds__(kBlock) void k_dmg_red(Ctl* ctl, const double* part, const int* bounds, int kind,
-                                                    double tol, int max_iter) {
-  __shared__ double red[8 * kWaves];
+constexpr int kRedBlock = kBlock;
+__global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* part, int n_tiles, const int* bounds,
+                                                       int kind, double tol, int max_iter) {
+  __shared__ double red[8 * (kRedBlock / 64)];
   Ctl* c = ctl + blockIdx.x;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
   double v[8] = {0.0, INFINITY, 0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < c->ntiles; k += kBlock) {
-    const double* pp = part + 8 * (c->tile0 + k);
-    v[PT_DELTA] += pp[PT_DELTA];
-    v[PT_AMIN] = fmin(v[PT_AMIN], pp[PT_AMIN]);
-    v[PT_GAMMA] += pp[PT_GAMMA];
-    v[PT_CF] = fmax(v[PT_CF], pp[PT_CF]);
-    v[PT_CA] = fmax(v[PT_CA], pp[PT_CA]);
-    v[PT_NA] += pp[PT_NA];
-    v[PT_RB] = fmax(v[PT_RB], pp[PT_RB]);
-    v[PT_CH] += pp[PT_CH];
+  const size_t nt = size_t(n_tiles);
+#pragma unroll 1
+  for (int k = c->tile0 + threadIdx.x; k < c->tile0 + c->ntiles; k += kRedBlock) {
+    v[PT_DELTA] += part[PT_DELTA * nt + k];
+    v[PT_AMIN] = fmin(v[PT_AMIN], part[PT_AMIN * nt + k]);
+    v[PT_GAMMA] += part[PT_GAMMA * nt + k];
+    v[PT_CF] = fmax(v[PT_CF], part[PT_CF * nt + k]);
+    v[PT_CA] = fmax(v[PT_CA], part[PT_CA * nt + k]);
+    v[PT_NA] += part[PT_NA * nt + k];
+    v[PT_RB] = fmax(v[PT_RB], part[PT_RB * nt + k]);
+    v[PT_CH] += part[PT_CH * nt + k];
   }
-  block_reduce<8, kPartOps>(v, red);
+  block_reduce_to0<8, kPartOps, kRedBlock / 64>(v, red);
   if (threadIdx.x != 0) return;
   const double sdel = v[PT_DELTA], samin = v[PT_AMIN], sgam = v[PT_GAMMA], scf = v[PT_CF], sca = v[PT_CA];
   const double sna = v[PT_NA], srb = v[PT_RB], sch = v[PT_CH];
@@ -509,7 +571,8 @@ __global__ __launch_bounds__(kBlock) void k_dmg_red(Ctl* ctl, const double* part
 // Final pass: bounds, active flags and statistics.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dmg_final(DmgArgs<T> a, uint8_t* active_out, pf_cg_stats_t* stats) {
-  const TileRec t = a.dm.tiles[blockIdx.x];
+  const int tile = tile_of_block(a.dm.n_tiles);
+  const TileRec t = a.dm.tiles[tile];
   const Ctl* c = a.ctl + t.inst;
   const InstP<T> P = a.ip[t.inst];
   const bool projected = (P.bounds == PF_BOUNDS_PROJECTED);
@@ -545,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg_final(DmgArgs<T> a, uint8_t* act
       if (active_out) active_out[g] = act;
     }
   }
-  if (stats && threadIdx.x == 0 && int(blockIdx.x) == c->tile0) {
+  if (stats && threadIdx.x == 0 && tile == c->tile0) {
     pf_cg_stats_t s;
     s.iters = c->iters;
     s.restarts = c->restarts;
@@ -604,13 +667,15 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
                        o->monotone);
     timer_end(m, 2, s);
   }
+  const int npt = (m->max_own + kBlock - 1) / kBlock;
+  auto kdmg = npt <= 1 ? k_dmg<T, 1> : (npt <= 2 ? k_dmg<T, 2> : (npt <= 4 ? k_dmg<T, 4> : k_dmg<T, 8>));
   auto round = [&]() {
     timer_begin(m, 1, s);
-    hipLaunchKernelGGL(k_dmg<T>, grid, block, lds, s, a);
+    hipLaunchKernelGGL(kdmg, grid, block, lds, s, a);
     timer_end(m, 1, s);
     timer_begin(m, 4, s);
-    hipLaunchKernelGGL(k_dmg_red, igrid, block, 0, s, m->dw.ctl, m->dw.part, m->dw.bounds, kind, o->tol,
-                       o->max_iter);
+    hipLaunchKernelGGL(k_dmg_red, igrid, dim3(kRedBlock), 0, s, m->dw.ctl, m->dw.part, m->n_tiles, m->dw.bounds,
+                       kind, o->tol, o->max_iter);
     timer_end(m, 4, s);
   };
   const int max_rounds = (o->check_every <= 0 && o->rounds > 0) ? std::min(o->rounds, o->max_iter) : o->max_iter;
@@ -618,17 +683,25 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
   if (o->check_every <= 0) {
     for (; launched < max_rounds; ++launched) round();
   } else {
-    // first poll after as many rounds as the last solve of this kind needed
-    // (solves of consecutive steps take similar counts), then every check_every
+    // first poll after two rounds more than the last solve of this kind
+    // needed (solves of consecutive steps take similar counts, and a round of
+    // a finished solve costs only two near-empty launches), then every
+    // check_every rounds
     const int last = m->last_rounds[kind == CG_QP ? 0 : 1];
-    int chunk = last > 0 ? std::min(std::max(last, 2), 64) : std::min(o->check_every, 8);
+    int chunk = last > 0 ? std::min(last + 2, 64) : std::min(o->check_every, 8);
     while (launched < max_rounds) {
       const int n = std::min(chunk, max_rounds - launched);
       for (int k = 0; k < n; ++k) round();
       launched += n;
       PF_HIP(hipGetLastError());
       PF_HIP(hipMemcpyAsync(m->ctl_pinned, m->dw.ctl, sizeof(Ctl) * m->n_inst, hipMemcpyDeviceToHost, s));
-      PF_HIP(hipStreamSynchronize(s));
+      PF_HIP(hipEventRecord(m->poll_ev, s));
+      // spin rather than block: the wait is short and a sleeping host thread
+      // wakes up tens of microseconds late
+      hipError_t q;
+      while ((q = hipEventQuery(m->poll_ev)) == hipErrorNotReady) {
+      }
+      if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
       bool all_done = true;
       for (int k = 0; k < m->n_inst; ++k) all_done = all_done && (m->ctl_pinned[k].mode == MODE_DONE);
       if (all_done) break;
@@ -640,8 +713,8 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
   timer_end(m, 2, s);
   PF_HIP(hipGetLastError());
   if (o->check_every > 0) {
-    PF_HIP(hipMemcpyAsync(m->ctl_pinned, m->dw.ctl, sizeof(Ctl) * m->n_inst, hipMemcpyDeviceToHost, s));
-    PF_HIP(hipStreamSynchronize(s));
+    // the last poll saw every instance done, or the round budget is spent:
+    // either way the control blocks it copied are final
     int flags = 0, rounds = 0;
     for (int k = 0; k < m->n_inst; ++k) {
       flags |= m->ctl_pinned[k].flags;

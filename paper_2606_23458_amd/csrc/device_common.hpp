@@ -34,6 +34,18 @@ inline StateOut<T> state_out(pf_state_t* s) {
   return StateOut<T>{(T*)s->ux, (T*)s->uy, (T*)s->vx, (T*)s->vy, (T*)s->ax, (T*)s->ay, (T*)s->d, (T*)s->H};
 }
 
+// Tile processed by this workgroup.  Workgroups are handed to the chip's
+// eight XCDs (each with its own L2) round-robin by workgroup id; this map
+// gives XCD x the contiguous x-th eighth of the tile list, which is a compact
+// region of the mesh (tiles are numbered in bisection order), so the halo
+// nodes and elements that neighbouring tiles share are fetched into one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int tile_of_block(int n_tiles) {
+  const int b = blockIdx.x;
+  const int q = n_tiles / kXcds, rr = n_tiles % kXcds, x = b % kXcds, i = b / kXcds;
+  return x * q + min(x, rr) + i;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -91,11 +103,12 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 
 // Several block-wide reductions at once, with one barrier: every wave
 // reduces each value by shuffles, lane 0 of each wave stores its results, and
-// every thread combines the waves in a fixed order.  OPS holds two bits per
-// value: 0 sum, 1 min, 2 max.  `sh` holds K * kWaves doubles and must not be
-// in use by another reduction of the same block.
-template <int K, uint32_t OPS>
-__device__ __forceinline__ void block_reduce(double (&v)[K], double* sh) {
+// thread 0 combines the waves in a fixed order (only thread 0's v holds the
+// block result).  OPS holds two bits per value: 0 sum, 1 min, 2 max.  NW is
+// the block's wave count; `sh` holds K * NW doubles and must not be in use by
+// another reduction of the block.
+template <int K, uint32_t OPS, int NW = kWaves>
+__device__ __forceinline__ void block_reduce_to0(double (&v)[K], double* sh) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint32_t op = (OPS >> (2 * k)) & 3u;
@@ -104,16 +117,17 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* sh) {
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) sh[k * kWaves + w] = v[k];
+    for (int k = 0; k < K; ++k) sh[k * NW + w] = v[k];
   }
   __syncthreads();
+  if (threadIdx.x != 0) return;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint32_t op = (OPS >> (2 * k)) & 3u;
-    double s = sh[k * kWaves];
+    double s = sh[k * NW];
 #pragma unroll
-    for (int j = 1; j < kWaves; ++j) {
-      const double y = sh[k * kWaves + j];
+    for (int j = 1; j < NW; ++j) {
+      const double y = sh[k * NW + j];
       s = op == 0 ? s + y : (op == 1 ? fmin(s, y) : fmax(s, y));
     }
     v[k] = s;

@@ -16,7 +16,7 @@ namespace pf {
 template <typename T, int S, int NPT>
 __global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> in,
                                                      StateOut<T> out, const T* __restrict__ fext) {
-  const TileRec t = dm.tiles[blockIdx.x];
+  const TileRec t = dm.tiles[tile_of_block(dm.n_tiles)];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;

@@ -230,6 +230,8 @@ static void free_all(pf_mesh_s* m) {
   m->allocs.clear();
   if (m->ctl_pinned) (void)hipHostFree(m->ctl_pinned);
   m->ctl_pinned = nullptr;
+  if (m->poll_ev) (void)hipEventDestroy(m->poll_ev);
+  m->poll_ev = nullptr;
   for (auto& t : m->timers)
     for (auto& e : t.ev) (void)hipEventDestroy(e);
 }
@@ -582,6 +584,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   {
     hipError_t e = hipHostMalloc((void**)&m->ctl_pinned, sizeof(Ctl) * n_instances, hipHostMallocDefault);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipHostMalloc"); }
+    e = hipEventCreateWithFlags(&m->poll_ev, hipEventDisableTiming);
+    if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipEventCreateWithFlags"); }
   }
   // tile counts per instance into the control blocks
   {
@@ -596,15 +600,15 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     hipError_t e = hipMemcpy(m->dw.ctl, c.data(), sizeof(Ctl) * n_instances, hipMemcpyHostToDevice);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipMemcpy"); }
   }
-  // LDS needs: explicit = 3 node values + 6 corner values; damage = 1 node value,
-  // then per element the larger of 3 FP64 corner values and 4 values of width w
+  // LDS needs: explicit = 3 node values + 6 corner values; damage = 1 node
+  // value + 3 corner values of width w (its FP64 and set-up passes chunk)
   int32_t max_loc = 0, max_te = 0;
   for (const TileRec& t : m->tiles_h) {
     max_loc = std::max(max_loc, t.n_own + t.n_halo);
     max_te = std::max(max_te, t.n_telem);
   }
   m->max_lds_explicit = int32_t((3 * size_t(max_loc) + 6 * size_t(max_te)) * w + 64);
-  m->max_lds_damage = int32_t(((size_t(max_loc) * w + 7) & ~size_t(7)) + size_t(max_te) * std::max<size_t>(24, 4 * w) + 64);
+  m->max_lds_damage = int32_t(((size_t(max_loc) * w + 7) & ~size_t(7)) + size_t(max_te) * 3 * w + 64);
   int dev = 0, lds_limit = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_limit <= 0)

@@ -132,6 +132,7 @@ struct pf_mesh_s {
   int32_t last_rounds[2] = {0, 0};   // CG rounds the last solve of each kind needed (sets the first poll)
   bool qp_started = false;           // a damage solve has been enqueued (resume is allowed)
   pf::Ctl* ctl_pinned = nullptr;     // pinned host copy of the control blocks
+  hipEvent_t poll_ev = nullptr;      // marks the copy of the control blocks (convergence polls)
   bool timing = false;
   pf::Timer timers[5];
 };

@@ -20,13 +20,13 @@ from .sim import Simulator, State, _stream
 
 
 def backward_step(sim: Simulator, s_n: State, s_np1: State, active_np1: torch.Tensor, adj_np1: State,
-                  adj_n: State, dGc: torch.Tensor) -> None:
+                  adj_n: State, dGc: torch.Tensor, cg=None, stats: torch.Tensor | None = None) -> None:
     """Adjoint of one staggered step (pf_step_backward); dGc (float64, device) is accumulated."""
     a, b, c, d = s_n.ptrs(), s_np1.ptrs(), adj_np1.ptrs(), adj_n.ptrs()
-    o = sim.cg_adj.opts()
+    o = (cg or sim.cg_adj).opts()
     L.call("pf_step_backward", sim.mesh.handle, sim.params, sim.dt, C.byref(a), C.byref(b),
-           active_np1.data_ptr(), C.byref(c), C.byref(d), dGc.data_ptr(), C.byref(o), sim.stats.data_ptr(),
-           _stream())
+           active_np1.data_ptr(), C.byref(c), C.byref(d), dGc.data_ptr(), C.byref(o),
+           (stats if stats is not None else sim.stats).data_ptr(), _stream())
 
 
 class TrajectoryRunner:
@@ -52,9 +52,10 @@ class TrajectoryRunner:
         # a checkpoint keeps the state, the held flags and the previous damage
         # field (the damage solve extrapolates from it)
         self.checkpoints = [(sim.state.clone(), sim.active.clone(), sim._next.d.clone())]
-        for n in range(self.steps):
-            sim.step()
-            if (n + 1) % self.K == 0 and n + 1 < self.steps:
+        for n0 in range(0, self.steps, self.K):
+            k = min(self.K, self.steps - n0)
+            sim.run(k, window=min(k, 25))
+            if n0 + k < self.steps:
                 self.checkpoints.append((sim.state.clone(), sim.active.clone(), sim._next.d.clone()))
         return sim.state
 
@@ -74,14 +75,49 @@ class TrajectoryRunner:
             ck_state, ck_active, ck_dprev = self.checkpoints[sgi]
             states[0].copy_(ck_state)
             self.seg_active[0].copy_(ck_active)
-            for j in range(k1 - k0):
-                states[j + 1].d.copy_(ck_dprev if j == 0 else states[j - 1].d)
-                sim.step_into(states[j], states[j + 1], self.seg_active[j + 1], self.seg_active[j])
-            for j in range(k1 - k0 - 1, -1, -1):
-                backward_step(sim, states[j], states[j + 1], self.seg_active[j + 1], cur, nxt, dGc)
-                cur, nxt = nxt, cur
+            self._recompute(k1 - k0, ck_dprev)
+            cur, nxt = self._reverse(k1 - k0, cur, nxt, dGc)
         self.adj = [cur, nxt]
         return dGc
+
+
+    # The recompute enqueues every step with a fixed budget of CG rounds and
+    # reads the solvers' statistics once at the end; a segment whose solves
+    # did not all finish is recomputed with convergence polling.
+    def _stats(self, n: int) -> torch.Tensor:
+        ni = self.sim.mesh.n_instances
+        if getattr(self, "_seg_stats", None) is None or self._seg_stats.shape[0] < n:
+            self._seg_stats = torch.zeros((n, ni * 6), dtype=torch.int32, device=self.sim.mesh.device)
+        return self._seg_stats
+
+    def _recompute(self, n: int, dprev0: torch.Tensor) -> None:
+        sim, states, act = self.sim, self.seg_states, self.seg_active
+        stats = self._stats(n)
+        budget = getattr(self, "_fwd_budget", 0) or 32
+        o = sim.cg.__class__(sim.cg.tol, sim.cg.max_iter, 0, sim.cg.start, sim.cg.monotone,
+                             min(budget, sim.cg.max_iter), 0)
+        for j in range(n):
+            states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
+            sim.explicit(states[j], states[j + 1])
+            sim.damage(states[j + 1].H, states[j].d, states[j + 1].d, act[j + 1], act[j], cg=o,
+                       stats=stats[j])
+        st = stats[:n].cpu().numpy().reshape(n, -1, 6)
+        if np.any(st[:, :, 3] != 0):
+            for j in range(n):
+                states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
+                sim.step_into(states[j], states[j + 1], act[j + 1], act[j])
+            self._fwd_budget = 0
+        else:
+            self._fwd_budget = int(st[:, :, 0].max()) + 4
+
+    def _reverse(self, n: int, cur: State, nxt: State, dGc: torch.Tensor):
+        # the adjoint solves warm-start from the previous step's multiplier, so
+        # they run polled, in order, and are never redone
+        sim, states, act = self.sim, self.seg_states, self.seg_active
+        for j in range(n - 1, -1, -1):
+            backward_step(sim, states[j], states[j + 1], act[j + 1], cur, nxt, dGc)
+            cur, nxt = nxt, cur
+        return cur, nxt
 
 
 class DamageTrajectory(torch.autograd.Function):

@@ -252,11 +252,12 @@ class Simulator:
 
     def damage(self, H: torch.Tensor, d_prev: torch.Tensor, d_out: torch.Tensor,
                active: torch.Tensor | None = None, guess: torch.Tensor | None = None,
-               cg: CgConfig | None = None) -> None:
+               cg: CgConfig | None = None, stats: torch.Tensor | None = None) -> None:
         """Damage update; `guess` seeds the held set (normally the previous step's flags)."""
         o = (cg or self.cg).opts()
         L.call("pf_damage_solve", self.mesh.handle, self.params, H.data_ptr(), d_prev.data_ptr(), d_out.data_ptr(),
-               _ptr(guess), _ptr(active), C.byref(o), self.stats.data_ptr(), _stream())
+               _ptr(guess), _ptr(active), C.byref(o), (stats if stats is not None else self.stats).data_ptr(),
+               _stream())
 
     def step_into(self, s_in: State, s_out: State, active_out: torch.Tensor, active_in: torch.Tensor | None) -> None:
         """One staggered step s_in -> s_out; active_in are the flags of the solve that produced s_in.d.
@@ -273,6 +274,52 @@ class Simulator:
             self.state, self._next = self._next, self.state
             self.active, self._active_next = self._active_next, self.active
             self.steps_done += 1
+        return self.state
+
+    def run(self, n: int, window: int = 16, margin: int = 4) -> State:
+        """n staggered steps with the solver's convergence read once per window of steps.
+
+        Each step enqueues the explicit step and a fixed budget of CG rounds
+        (check_every = 0, so the host never waits inside a step); the budget
+        is the largest round count of the previous window plus `margin`.
+        After a window the per-step statistics are read once: if a solve did
+        not finish within its budget, the window is rolled back to its first
+        state and re-run with step(), which polls.  Rounds after a solve has
+        finished do nothing, so the states equal those of step(n) bit for bit.
+        """
+        ni = self.mesh.n_instances
+        if getattr(self, "_win_stats", None) is None or self._win_stats.shape[0] < window:
+            self._win_stats = torch.zeros((window, ni * 6), dtype=torch.int32, device=self.mesh.device)
+        budget = getattr(self, "_budget", 0) or 32
+        done = 0
+        while done < n:
+            w = min(window, n - done)
+            refs = (self.state, self._next, self.active, self._active_next)
+            snap = (self.state.clone(), self._next.d.clone(), self.active.clone())
+            o = C.byref(CgConfig(self.cg.tol, self.cg.max_iter, 0, self.cg.start, self.cg.monotone,
+                                 min(budget, self.cg.max_iter), 0).opts())
+            for k in range(w):
+                self.explicit(self.state, self._next)
+                L.call("pf_damage_solve", self.mesh.handle, self.params, self._next.H.data_ptr(),
+                       self.state.d.data_ptr(), self._next.d.data_ptr(), self.active.data_ptr(),
+                       self._active_next.data_ptr(), o, self._win_stats[k].data_ptr(), _stream())
+                self.state, self._next = self._next, self.state
+                self.active, self._active_next = self._active_next, self.active
+            st = self._win_stats[:w].cpu().numpy().reshape(w, ni, 6)
+            if np.any(st[:, :, 3] != 0):
+                # a solve did not finish within the budget: redo the window, polling
+                self.state, self._next, self.active, self._active_next = refs
+                self.state.copy_(snap[0])
+                self._next.d.copy_(snap[1])
+                self.active.copy_(snap[2])
+                self.step(w)
+                budget = max(s["iters"] for s in self.cg_stats()) + 2 * margin
+            else:
+                self.stats.copy_(self._win_stats[w - 1])
+                self.steps_done += w
+                budget = int(st[:, :, 0].max()) + margin
+            done += w
+        self._budget = budget
         return self.state
 
     def cg_stats(self) -> list[dict]:
@@ -306,16 +353,20 @@ class GraphStepper:
     build a new stepper after changing them.
     """
 
-    def __init__(self, sim: Simulator, rounds: int = 24, more: int = 8):
+    def __init__(self, sim: Simulator, rounds: int | None = None, more: int = 4):
         self.sim = sim
         base = sim.cg
-        first = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, rounds, 0)
-        cont = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, more, 1)
         self.max_iter = base.max_iter
         # one eager step so the device holds this simulator's parameters (a
-        # captured call must not upload anything)
+        # captured call must not upload anything); by default the first graph
+        # holds four rounds more than that step's solve needed
         sim.step()
         torch.cuda.synchronize()
+        if rounds is None:
+            rounds = max(s["iters"] for s in sim.cg_stats()) + 4
+        self.rounds, self.more = rounds, more
+        first = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, rounds, 0)
+        cont = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, more, 1)
         self._params = bytes(sim.params)
         self._dt = list(sim.dt)
         self.states = (sim.state, sim._next)

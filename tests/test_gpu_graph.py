@@ -41,3 +41,33 @@ def test_graph_continuation_rounds_equal_eager():
 
 def test_graph_batched_fp32():
     _pair(w.config4(64)[:3], "f32", rounds=24, more=8, steps=6)
+
+
+@pytest.mark.parametrize("budget", [None, 3])
+def test_windowed_run_equals_step(budget):
+    """run() (convergence read once per window) gives step()'s states bit for bit;
+    a budget of 3 rounds forces the roll-back path."""
+    from paper_2606_23458_amd import Simulator
+    p = w.small_plate(40, 20, seed=5)
+    a = Simulator(p, dtype="f64")
+    b = Simulator(p, dtype="f64", dt=list(a.dt))
+    a.step(14)
+    if budget is not None:
+        b._budget = budget
+    b.run(14, window=5)
+    torch.cuda.synchronize()
+    assert b.steps_done == 14
+    assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
+    assert torch.equal(a.active, b.active)
+    assert torch.equal(a._next.d, b._next.d)
+
+
+def test_windowed_run_batched_fp32():
+    from paper_2606_23458_amd import Simulator
+    probs = w.config4(64)[:4]
+    a = Simulator(probs, dtype="f32")
+    b = Simulator(probs, dtype="f32", dt=list(a.dt))
+    a.step(20)
+    b.run(20, window=8)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
