@@ -88,7 +88,10 @@ typedef struct {
 
 /* Tile plan options; NULL selects the defaults. */
 typedef struct {
-    int32_t tile_nodes;      /* owned nodes per tile, 64..2048; 0 = default (512) */
+    int32_t tile_nodes;      /* owned nodes per tile, 64..2048; 0 = default (512 in
+                                FP32, 256 in FP64) */
+    int32_t explicit_block;  /* workgroup size of the explicit-step kernel: 256 or 512;
+                                0 = default (256) */
 } pf_tile_opts_t;
 
 /* Material and model of one instance (Sec. 2.1-2.2).  Geometry-independent. */
@@ -271,11 +274,13 @@ pf_status_t pf_cfl_dt(pf_mesh_t m, const pf_params_t* p, double factor, double* 
 /*
  * Tile-size autotuning (a set-up call, not part of the method; it allocates).
  * For each candidate owned-node count per tile it builds the tile plan of the
- * given meshes, times `reps` explicit steps from a zero state and `reps`
- * damage CG rounds (the four launches of one CG iteration, on a linear solve
- * over all nodes), and scores the plan as
+ * given meshes, times `reps` explicit steps from a zero state (with 256- and
+ * with 512-thread workgroups, keeping the faster) and `reps` damage CG rounds
+ * (the launches of one CG iteration, on a linear solve over all nodes), and
+ * scores the plan as
  *     explicit_us + cg_rounds_per_step * cg_round_us.
- * The smallest score wins; pass out->best as pf_tile_opts_t.tile_nodes.
+ * The smallest score wins; pass out->best and out->best_explicit_block as
+ * pf_tile_opts_t.tile_nodes and .explicit_block.
  * Candidates whose tiles need more LDS than a workgroup may use are skipped
  * (status PF_ERR_UNSUPPORTED).  `inst`, `n_instances`, `dtype` and `p` are as
  * for pf_mesh_create and pf_explicit_step.  Synchronous on `stream`; the
@@ -293,10 +298,12 @@ typedef struct {
 
 typedef struct {
     int32_t best;                       /* the chosen tile_nodes */
+    int32_t best_explicit_block;        /* the chosen pf_tile_opts_t.explicit_block */
     int32_t n_tried;                    /* candidates tried (entries filled below) */
     int32_t tile_nodes[PF_TUNE_MAX];
     int32_t status[PF_TUNE_MAX];        /* pf_status_t of each candidate's plan */
-    double explicit_us[PF_TUNE_MAX];    /* mean explicit-step time */
+    int32_t explicit_block[PF_TUNE_MAX];/* the faster explicit workgroup size (256, 512) */
+    double explicit_us[PF_TUNE_MAX];    /* mean explicit-step time with that workgroup size */
     double cg_round_us[PF_TUNE_MAX];    /* mean damage CG round time */
     double score_us[PF_TUNE_MAX];
 } pf_tune_result_t;

@@ -167,12 +167,17 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   // residual is then accurate to the rounding of x, not of an FP32 matvec) a
   // chunk of elements at a time; the set-up sweep uses the same space for
   // diagonal corners and loads
-  unsigned char* rest = smem + ((size_t(nloc) * sizeof(T) + 7) & ~size_t(7));
+  uint16_t* coffs = reinterpret_cast<uint16_t*>(sv + nloc);   // [n_own + 1] corner-list offsets
+  uint16_t* clist = coffs + t.n_own + 1;                     // [n_corner] corner ids
+  unsigned char* rest =
+      smem + ((size_t(nloc) * sizeof(T) + 2 * (size_t(t.n_own) + 1 + size_t(t.n_corner)) + 7) & ~size_t(7));
   T* qc = reinterpret_cast<T*>(rest);          // [3 n_telem] (first, iterate)
   double* qd = reinterpret_cast<double*>(rest); // [3 chunk]   (restart, check)
   T* dc = reinterpret_cast<T*>(rest);          // [3 chunk]   diagonal corners (set-up)
   T* bc = dc;                                  // [chunk] from offset 3 chunk: load per corner (set-up)
   const int tid = threadIdx.x;
+
+  stage_corners(a.dm, t, coffs, clist);
 
   // ---- phase 1: the vector to multiply, on owned and halo nodes -------------
   double amin = INFINITY, ch = 0.0;
@@ -272,10 +277,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       for (int r = 0; r < NPT; ++r) {
         const int i = tid + r * kBlock;
         if (i < t.n_own) {
-          const int g = t.node_begin + i;
-          const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+          const int j0 = coffs[i], j1 = coffs[i + 1];
           for (int j = j0; j < j1; ++j) {
-            const int cc = a.dm.lcorner[j];
+            const int cc = clist[j];
             const int e = cc / 3;
             if (e >= e0 && e < e1) {
               dacc[r] += dc[cc - 3 * e0];
@@ -332,10 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       for (int r = 0; r < NPT; ++r) {
         const int i = tid + r * kBlock;
         if (i < t.n_own) {
-          const int g = t.node_begin + i;
-          const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+          const int j0 = coffs[i], j1 = coffs[i + 1];
           for (int j = j0; j < j1; ++j) {
-            const int cc = a.dm.lcorner[j];
+            const int cc = clist[j];
             const int e = cc / 3;
             if (e >= e0 && e < e1) qacc[r] += qd[cc - 3 * e0];
           }
@@ -414,9 +417,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     const T* rz = iter ? rn_ : rc;
     for (int i = tid; i < t.n_own; i += kBlock) {
       const int g = t.node_begin + i;
-      const int j0 = a.dm.lrow[g], j1 = a.dm.lrow[g + 1];
+      const int j0 = coffs[i], j1 = coffs[i + 1];
       T qi = T(0);
-      for (int j = j0; j < j1; ++j) qi += qc[a.dm.lcorner[j]];
+      for (int j = j0; j < j1; ++j) qi += qc[clist[j]];
       wn[g] = qi;
       const T zv = sv[i];
       const T rv = rz[g];

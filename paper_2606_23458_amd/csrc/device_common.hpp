@@ -46,6 +46,16 @@ __device__ __forceinline__ int tile_of_block(int n_tiles) {
   return x * q + min(x, rr) + i;
 }
 
+// Stage the owned nodes' corner lists of a tile in LDS: offs[i] .. offs[i+1]
+// index node i's entries of cl, which are tile-local corner ids 3 e + k in
+// ascending element id.  Coalesced loads by the whole block; the caller
+// synchronises before reading.
+__device__ __forceinline__ void stage_corners(const DevMesh& dm, const TileRec& t, uint16_t* offs, uint16_t* cl) {
+  for (int i = threadIdx.x; i <= t.n_own; i += blockDim.x)
+    offs[i] = uint16_t(dm.lrow[t.node_begin + i] - t.corner_begin);
+  for (int k = threadIdx.x; k < t.n_corner; k += blockDim.x) cl[k] = dm.lcorner[t.corner_begin + k];
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

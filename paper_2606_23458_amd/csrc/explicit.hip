@@ -13,9 +13,9 @@
 
 namespace pf {
 
-template <typename T, int S, int NPT>
-__global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> in,
-                                                     StateOut<T> out, const T* __restrict__ fext) {
+template <typename T, int S, int NPT, int BS>
+__global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> in,
+                                                 StateOut<T> out, const T* __restrict__ fext) {
   const TileRec t = dm.tiles[tile_of_block(dm.n_tiles)];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
@@ -25,13 +25,16 @@ __global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>*
   T* sd = suy + nloc;
   T* sfx = sd + nloc;
   T* sfy = sfx + 3 * t.n_telem;
+  uint16_t* coffs = reinterpret_cast<uint16_t*>(sfy + 3 * t.n_telem);   // [n_own + 1] corner-list offsets
+  uint16_t* clist = coffs + t.n_own + 1;                                // [n_corner] corner ids
   const int tid = threadIdx.x;
+  stage_corners(dm, t, coffs, clist);
 
   // ---- phase 1: predictor (eq. vv_u) -------------------------------------
   T rvx[NPT], rvy[NPT], rax[NPT], ray[NPT];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int i = tid + r * kBlock;
+    const int i = tid + r * BS;
     if (i < t.n_own) {
       const int g = t.node_begin + i;
       const T vx = in.vx[g], vy = in.vy[g], ax = in.ax[g], ay = in.ay[g];
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>*
       rvx[r] = vx, rvy[r] = vy, rax[r] = ax, ray[r] = ay;
     }
   }
-  for (int i = t.n_own + tid; i < nloc; i += kBlock) {
+  for (int i = t.n_own + tid; i < nloc; i += BS) {
     const int g = dm.halo_idx[t.halo_begin + (i - t.n_own)];
     sux[i] = in.ux[g] + P.dt * in.vx[g] + P.half_dt2 * in.ax[g];
     suy[i] = in.uy[g] + P.dt * in.vy[g] + P.half_dt2 * in.ay[g];
@@ -56,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>*
   // ---- phase 2: element strain, split, stress, corner forces, history ------
   const T* __restrict__ geo = static_cast<const T*>(dm.geo);
   const size_t nte = size_t(dm.n_te);
-  for (int e = tid; e < t.n_telem; e += kBlock) {
+  for (int e = tid; e < t.n_telem; e += BS) {
     const int te = t.telem_begin + e;
     const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
     const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
@@ -89,13 +92,13 @@ __global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>*
   const size_t N = size_t(dm.n_nodes);
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
-    const int i = tid + r * kBlock;
+    const int i = tid + r * BS;
     if (i < t.n_own) {
       const int g = t.node_begin + i;
-      const int j0 = dm.lrow[g], j1 = dm.lrow[g + 1];
+      const int j0 = coffs[i], j1 = coffs[i + 1];
       T fx = T(0), fy = T(0);
       for (int j = j0; j < j1; ++j) {
-        const int c = dm.lcorner[j];
+        const int c = clist[j];
         fx += sfx[c];
         fy += sfy[c];
       }
@@ -116,21 +119,32 @@ __global__ __launch_bounds__(kBlock) void k_explicit(DevMesh dm, const InstP<T>*
 template <typename T, int S>
 static hipError_t launch_explicit_s(pf_mesh_s* m, const pf_state_t* in, pf_state_t* out, const void* fext,
                                     hipStream_t s) {
-  const int npt = (m->max_own + kBlock - 1) / kBlock;
   const size_t lds = m->max_lds_explicit;
   const InstP<T>* ip = static_cast<const InstP<T>*>(m->dw.instp);
   auto si = state_in<T>(in);
   auto so = state_out<T>(out);
   const T* fe = static_cast<const T*>(fext);
-  dim3 grid(m->n_tiles), block(kBlock);
-  if (npt <= 1)
-    hipLaunchKernelGGL((k_explicit<T, S, 1>), grid, block, lds, s, m->dm, ip, si, so, fe);
-  else if (npt <= 2)
-    hipLaunchKernelGGL((k_explicit<T, S, 2>), grid, block, lds, s, m->dm, ip, si, so, fe);
-  else if (npt <= 4)
-    hipLaunchKernelGGL((k_explicit<T, S, 4>), grid, block, lds, s, m->dm, ip, si, so, fe);
-  else
-    hipLaunchKernelGGL((k_explicit<T, S, 8>), grid, block, lds, s, m->dm, ip, si, so, fe);
+  const dim3 grid(m->n_tiles);
+  if (m->explicit_block == 512) {
+    const int npt = (m->max_own + 511) / 512;
+    if (npt <= 1)
+      hipLaunchKernelGGL((k_explicit<T, S, 1, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe);
+    else if (npt <= 2)
+      hipLaunchKernelGGL((k_explicit<T, S, 2, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe);
+    else
+      hipLaunchKernelGGL((k_explicit<T, S, 4, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe);
+  } else {
+    const int npt = (m->max_own + kBlock - 1) / kBlock;
+    const dim3 block(kBlock);
+    if (npt <= 1)
+      hipLaunchKernelGGL((k_explicit<T, S, 1, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+    else if (npt <= 2)
+      hipLaunchKernelGGL((k_explicit<T, S, 2, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+    else if (npt <= 4)
+      hipLaunchKernelGGL((k_explicit<T, S, 4, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+    else
+      hipLaunchKernelGGL((k_explicit<T, S, 8, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+  }
   return hipGetLastError();
 }
 

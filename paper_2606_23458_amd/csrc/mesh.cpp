@@ -244,6 +244,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   if (dtype != PF_F32 && dtype != PF_F64) return fail(PF_ERR_ARG, "dtype must be PF_F32 or PF_F64");
   int tile_nodes = (tile && tile->tile_nodes > 0) ? tile->tile_nodes : (dtype == PF_F64 ? 256 : 512);
   if (tile_nodes < 64 || tile_nodes > kMaxTileNodes) return fail(PF_ERR_ARG, "tile_nodes must be in [64, 2048]");
+  const int explicit_block = (tile && tile->explicit_block > 0) ? tile->explicit_block : kBlock;
+  if (explicit_block != 256 && explicit_block != 512) return fail(PF_ERR_ARG, "explicit_block must be 256 or 512");
 
   // ---- validate and count -------------------------------------------------
   int64_t n_tot = 0, e_tot = 0;
@@ -260,6 +262,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   pf_mesh_s* m = new (std::nothrow) pf_mesh_s();
   if (!m) return fail(PF_ERR_NOMEM, "host allocation failed");
   m->dtype = dtype;
+  m->explicit_block = explicit_block;
   m->n_inst = n_instances;
   m->n_nodes = int32_t(n_tot);
   m->n_elems = int32_t(e_tot);
@@ -473,6 +476,11 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     elem_off += ne;
   }
   for (int64_t i = 0; i < n_tot; ++i) lrow[i + 1] += lrow[i];
+  for (TileRec& t : m->tiles_h) {
+    t.corner_begin = lrow[t.node_begin];
+    t.n_corner = lrow[t.node_begin + t.n_own] - t.corner_begin;
+    m->max_corner = std::max(m->max_corner, t.n_corner);
+  }
   m->n_tiles = int32_t(m->tiles_h.size());
   m->n_te = int32_t(te_gid.size());
 
@@ -506,6 +514,10 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
         for (int32_t j = lrow[g]; j < lrow[g + 1] && bad.empty(); ++j)
           if (lcorner[j] >= 3 * t.n_telem) bad = "corner id";
       }
+      // the kernels stage the corner lists in LDS with 16-bit offsets
+      if (bad.empty() && (t.n_corner < t.n_own || t.n_corner > 65535 || t.corner_begin != lrow[t.node_begin] ||
+                          t.corner_begin + t.n_corner != lrow[t.node_begin + t.n_own]))
+        bad = "tile corner range";
     }
     if (bad.empty() && covered != m->n_nodes) bad = "tiles do not cover the nodes";
     if (bad.empty() && lrow[n_tot] != int32_t(lcorner.size())) bad = "corner list size";
@@ -607,8 +619,10 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     max_loc = std::max(max_loc, t.n_own + t.n_halo);
     max_te = std::max(max_te, t.n_telem);
   }
-  m->max_lds_explicit = int32_t((3 * size_t(max_loc) + 6 * size_t(max_te)) * w + 64);
-  m->max_lds_damage = int32_t(((size_t(max_loc) * w + 7) & ~size_t(7)) + size_t(max_te) * 3 * w + 64);
+  // plus, in both, the owned nodes' corner lists (16-bit offsets and ids)
+  const size_t lists = 2 * (size_t(m->max_own) + 1 + size_t(m->max_corner));
+  m->max_lds_explicit = int32_t((3 * size_t(max_loc) + 6 * size_t(max_te)) * w + lists + 64);
+  m->max_lds_damage = int32_t(((size_t(max_loc) * w + lists + 7) & ~size_t(7)) + size_t(max_te) * 3 * w + 64);
   int dev = 0, lds_limit = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_limit <= 0)

@@ -29,7 +29,8 @@ struct TileRec {
   int32_t own_elem_begin;  // internal id of the first owned element
   int32_t inst;            // instance
   int32_t lds_bytes;       // dynamic LDS this tile needs (explicit kernel, FP64 upper bound)
-  int32_t pad0, pad1;
+  int32_t corner_begin;    // first entry of the owned nodes' corner lists (lcorner index)
+  int32_t n_corner;        // entries in the owned nodes' corner lists
 };
 
 // Per-instance constants for the kernels, in the arithmetic type T.
@@ -118,6 +119,8 @@ struct pf_mesh_s {
   pf_dtype_t dtype;
   int32_t n_inst = 0, n_nodes = 0, n_elems = 0, n_tiles = 0, n_te = 0;
   int32_t max_tile_nodes = 0, max_tile_elems = 0, max_own = 0, max_lds_explicit = 0, max_lds_damage = 0;
+  int32_t max_corner = 0;
+  int32_t explicit_block = 256;      // workgroup size of the explicit-step kernel (256 or 512)
   int32_t split = -1;
   std::vector<pf_instance_info_t> info;
   std::vector<int32_t> node_perm, elem_perm;

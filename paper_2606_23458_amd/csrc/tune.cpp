@@ -36,9 +36,10 @@ constexpr int kDefaultCandidates[] = {128, 192, 256, 384, 512, 768, 1024};
 
 // Time `reps` explicit steps and `reps` damage CG rounds of one tile plan.
 pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dtype, const pf_params_t* p,
-                      int32_t tile_nodes, int32_t reps, hipStream_t s, double* explicit_us, double* round_us) {
+                      int32_t tile_nodes, int32_t reps, hipStream_t s, double* explicit_us, int32_t* explicit_block,
+                      double* round_us) {
   Handle h;
-  pf_tile_opts_t to{tile_nodes};
+  pf_tile_opts_t to{tile_nodes, 0};
   pf_status_t st = pf_mesh_create(inst, n_inst, dtype, &to, s, &h.m);
   if (st != PF_OK) return st;
   pf_mesh_s* m = h.m;
@@ -61,17 +62,25 @@ pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dty
   Events ev;
   PF_HIP(hipEventCreate(&ev.a));
   PF_HIP(hipEventCreate(&ev.b));
-  // explicit step
-  for (int k = 0; k < 2; ++k)
-    if ((st = pf_explicit_step(m, p, dt.data(), &st2[k & 1], &st2[(k + 1) & 1], nullptr, s)) != PF_OK) return st;
-  PF_HIP(hipEventRecord(ev.a, s));
-  for (int k = 0; k < reps; ++k)
-    if ((st = pf_explicit_step(m, p, dt.data(), &st2[k & 1], &st2[(k + 1) & 1], nullptr, s)) != PF_OK) return st;
-  PF_HIP(hipEventRecord(ev.b, s));
-  PF_HIP(hipEventSynchronize(ev.b));
+  // explicit step, with each workgroup size
   float ms = 0.f;
-  PF_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-  *explicit_us = 1e3 * double(ms) / reps;
+  *explicit_us = 0.0;
+  for (int bs : {256, 512}) {
+    m->explicit_block = bs;
+    for (int k = 0; k < 2; ++k)
+      if ((st = pf_explicit_step(m, p, dt.data(), &st2[k & 1], &st2[(k + 1) & 1], nullptr, s)) != PF_OK) return st;
+    PF_HIP(hipEventRecord(ev.a, s));
+    for (int k = 0; k < reps; ++k)
+      if ((st = pf_explicit_step(m, p, dt.data(), &st2[k & 1], &st2[(k + 1) & 1], nullptr, s)) != PF_OK) return st;
+    PF_HIP(hipEventRecord(ev.b, s));
+    PF_HIP(hipEventSynchronize(ev.b));
+    PF_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    const double us = 1e3 * double(ms) / reps;
+    if (*explicit_us == 0.0 || us < *explicit_us) {
+      *explicit_us = us;
+      *explicit_block = bs;
+    }
+  }
   // damage CG rounds: a linear solve on all nodes with a positive right-hand
   // side (every byte 0x3f is a positive finite value in either width), run
   // for a fixed number of rounds without synchronising
@@ -129,17 +138,20 @@ extern "C" pf_status_t pf_tune_tiles(const pf_mesh_desc_t* inst, int32_t n_insta
   for (size_t k = 0; k < cand.size(); ++k) {
     out->tile_nodes[k] = cand[k];
     double te = 0.0, tr = 0.0;
-    const pf_status_t st = time_plan(inst, n_instances, dtype, p, cand[k], reps, s, &te, &tr);
+    int32_t eb = 256;
+    const pf_status_t st = time_plan(inst, n_instances, dtype, p, cand[k], reps, s, &te, &eb, &tr);
     out->status[k] = st;
     out->n_tried = int32_t(k + 1);
     if (st == PF_ERR_UNSUPPORTED) continue;   // the plan needs more LDS than a workgroup has
     if (st != PF_OK) return st;               // a real error: pf_last_error() holds its text
     out->explicit_us[k] = te;
+    out->explicit_block[k] = eb;
     out->cg_round_us[k] = tr;
     out->score_us[k] = te + weight * tr;
     if (out->best == 0 || out->score_us[k] < best) {
       best = out->score_us[k];
       out->best = cand[k];
+      out->best_explicit_block = eb;
     }
   }
   if (out->best == 0) return fail(PF_ERR_UNSUPPORTED, "no candidate tile size fits the device's LDS");

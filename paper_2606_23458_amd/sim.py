@@ -36,7 +36,8 @@ class Mesh:
     ``fixed`` (N,2) uint8 arrays (for example workloads.Problem).
     """
 
-    def __init__(self, meshes, dtype: str = "f64", tile_nodes: int = 0, device: str = "cuda"):
+    def __init__(self, meshes, dtype: str = "f64", tile_nodes: int = 0, device: str = "cuda",
+                 explicit_block: int = 0):
         if dtype not in ("f32", "f64"):
             raise ValueError(dtype)
         self.dtype_code = dtype
@@ -53,7 +54,7 @@ class Mesh:
             descs[k] = L.MeshDesc(len(xy), len(tri), xy.ctypes.data, tri.ctypes.data,
                                   None if fx is None else fx.ctypes.data)
         h = C.c_void_p()
-        opts = L.TileOpts(int(tile_nodes))
+        opts = L.TileOpts(int(tile_nodes), int(explicit_block))
         L.call("pf_mesh_create", descs, n, L.PF_F64 if dtype == "f64" else L.PF_F32, C.byref(opts),
                _stream(), C.byref(h))
         self.handle = h
@@ -200,10 +201,12 @@ class Simulator:
             problems = [problems]
         self.problems = list(problems)
         self.dtype_code = dtype or self.problems[0].dtype
+        explicit_block = 0
         if mesh is None and tile_nodes == "auto":
             from .tune import tune_tiles
-            tile_nodes = tune_tiles(self.problems, self.dtype_code)["best"]
-        self.mesh = mesh or Mesh(self.problems, self.dtype_code, tile_nodes)
+            rep = tune_tiles(self.problems, self.dtype_code)
+            tile_nodes, explicit_block = rep["best"], rep["explicit_block"]
+        self.mesh = mesh or Mesh(self.problems, self.dtype_code, tile_nodes, explicit_block=explicit_block)
         n = len(self.problems)
         self.params = (L.Params * n)(*[params_of(p) for p in self.problems])
         self.dt = (C.c_double * n)()

@@ -32,7 +32,7 @@ def test_struct_layouts_match_header(tmp_path):
     prog = tmp_path / "sizes.c"
     checks = {
         "pf_mesh_desc_t": (L.MeshDesc, ["n_nodes", "n_elems", "xy", "tri", "fixed"]),
-        "pf_tile_opts_t": (L.TileOpts, ["tile_nodes"]),
+        "pf_tile_opts_t": (L.TileOpts, ["tile_nodes", "explicit_block"]),
         "pf_params_t": (L.Params, ["E", "nu", "rho", "Gc", "l0", "eta", "gamma_star", "model", "split", "plane",
                                    "bounds"]),
         "pf_state_t": (L.StatePtrs, ["ux", "uy", "vx", "vy", "ax", "ay", "d", "H"]),
@@ -43,8 +43,8 @@ def test_struct_layouts_match_header(tmp_path):
         "pf_mesh_totals_t": (L.Totals, ["n_instances", "n_nodes", "n_elems", "n_tiles", "dtype", "max_tile_nodes",
                                         "max_tile_elems", "tile_elems_total", "device_bytes"]),
         "pf_tune_opts_t": (L.TuneOpts, ["n_candidates", "tile_nodes", "reps", "cg_rounds_per_step"]),
-        "pf_tune_result_t": (L.TuneResult, ["best", "n_tried", "tile_nodes", "status", "explicit_us", "cg_round_us",
-                                            "score_us"]),
+        "pf_tune_result_t": (L.TuneResult, ["best", "best_explicit_block", "n_tried", "tile_nodes", "status",
+                                            "explicit_block", "explicit_us", "cg_round_us", "score_us"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for t, (_, fields) in checks.items():
@@ -98,6 +98,11 @@ def test_argument_errors():
     assert st == L.PF_ERR_ARG
     st, msg = _create(xy, np.array([[0, 1, 2]]), tile=5000)
     assert st == L.PF_ERR_ARG and "tile_nodes" in msg
+    keep = [np.ascontiguousarray(xy, np.float64), np.ascontiguousarray([[0, 1, 2]], np.int32)]
+    descs = (L.MeshDesc * 1)(L.MeshDesc(3, 1, keep[0].ctypes.data, keep[1].ctypes.data, None))
+    h = C.c_void_p()
+    assert lib.pf_mesh_create(descs, 1, 0, C.byref(L.TileOpts(0, 384)), None, C.byref(h)) == L.PF_ERR_ARG
+    assert "explicit_block" in lib.pf_last_error().decode()
     assert lib.pf_mesh_create(None, 1, 0, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_explicit_step(None, None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_damage_solve(None, None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG

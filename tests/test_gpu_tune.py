@@ -42,3 +42,15 @@ def test_tuner_batched_handle():
     rep = tune_tiles(probs, "f32", candidates=[256, 512], reps=3)
     assert rep["best"] in (256, 512)
     assert np.all([r["score_us"] > 0 for r in rep["candidates"]])
+
+
+def test_explicit_workgroup_sizes_agree_bitwise():
+    """256- and 512-thread explicit-step workgroups compute the same sums in the same order."""
+    from paper_2606_23458_amd import Mesh, Simulator
+    p = w.small_plate(48, 24, seed=2)
+    a = Simulator(p, dtype="f64", mesh=Mesh([p], "f64", 128, explicit_block=256))
+    b = Simulator(p, dtype="f64", mesh=Mesh([p], "f64", 128, explicit_block=512), dt=list(a.dt))
+    a.step(6)
+    b.step(6)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
