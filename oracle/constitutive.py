@@ -47,6 +47,46 @@ def wave_speed(E: float, nu: float, rho: float, plane: str) -> float:
     return math.sqrt((k["lam"] + 2.0 * k["mu"]) / rho)
 
 
+def shear_wave_speed(E: float, nu: float, rho: float) -> float:
+    """Shear wave speed c_s = sqrt(mu/rho) (the same in both plane assumptions)."""
+    return math.sqrt(elastic_constants(E, nu, "strain")["mu"] / rho)
+
+
+def rayleigh_speed(E: float, nu: float, rho: float, plane: str) -> float:
+    """Rayleigh surface-wave speed c_R of the plane's 2D elastic medium.
+
+    c_R = xi c_s, where xi in (0, 1) is the root of the Rayleigh equation
+        (2 - xi^2)^2 = 4 sqrt(1 - xi^2) sqrt(1 - kappa xi^2),  kappa = c_s^2 / c_p^2,
+    with c_p the plane's dilatational speed.  Found by bisection: the function
+    f(xi) = (2 - xi^2)^2 - 4 sqrt(1 - xi^2) sqrt(1 - kappa xi^2) behaves like
+    -2 (1 - kappa) xi^2 < 0 near 0 and equals 1 at xi = 1; its one root in
+    (0, 1) (besides xi = 0) lies above 0.5 for 0 < kappa < 1/2.
+    """
+    cs = shear_wave_speed(E, nu, rho)
+    cp = wave_speed(E, nu, rho, plane)
+    kappa = (cs / cp) ** 2
+
+    def f(x):
+        return (2.0 - x * x) ** 2 - 4.0 * math.sqrt(1.0 - x * x) * math.sqrt(1.0 - kappa * x * x)
+
+    lo, hi = 0.5, 1.0
+    assert f(lo) < 0.0 < f(hi)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) < 0.0:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo < 1e-16:
+            break
+    return 0.5 * (lo + hi) * cs
+
+
+def subcycle_limit(E: float, nu: float, rho: float, plane: str) -> int:
+    """Largest admissible damage subcycling factor N_max = floor(c_p / (0.6 c_R)) (Sec. 2.3, subcycling)."""
+    return int(math.floor(wave_speed(E, nu, rho, plane) / (0.6 * rayleigh_speed(E, nu, rho, plane))))
+
+
 def _pos(x):
     return torch.where(x > 0, x, torch.zeros_like(x))
 

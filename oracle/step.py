@@ -127,8 +127,12 @@ class Sim:
                               zero_n if lt is None else lt.detach().numpy())
         return fwAD.make_dual(out, torch.from_numpy(tan)), act, upper
 
-    def step(self, st: State, Gc=None, f_ext=None, info: dict | None = None) -> State:
+    def step(self, st: State, Gc=None, f_ext=None, info: dict | None = None, solve: bool = True) -> State:
+        """One staggered step; with solve=False the damage sub-problem is skipped (subcycling:
+        d_{n+1} = d_n while the mechanics and the history field advance)."""
         u1, v1, a1, H1, _ = self.explicit(st, f_ext)
+        if not solve:
+            return State(u1, v1, a1, st.d, H1)
         d1, act, upper = self.damage(H1, st.d, self.mat.Gc if Gc is None else Gc)
         if info is not None:
             info["active"] = act
@@ -153,15 +157,22 @@ def staggered_step(problem, st: State, dt: float | None = None) -> State:
 
 
 def run(problem, steps: int | None = None, Gc: float | None = None, dt: float | None = None,
-        state: State | None = None, record_every: int = 0, sim: Sim | None = None):
-    """Integrate ``steps`` staggered steps; returns (final State, recorded states, sim)."""
+        state: State | None = None, record_every: int = 0, sim: Sim | None = None, n_sub: int = 1):
+    """Integrate ``steps`` staggered steps; returns (final State, recorded states, sim).
+
+    With n_sub > 1 the damage sub-problem is solved only on every n_sub-th
+    step (steps n_sub, 2 n_sub, ... counted from 1), as in the paper's
+    subcycling (Sec. 2.3); the history field is updated every step.
+    """
+    if n_sub < 1:
+        raise ValueError("n_sub must be >= 1")
     sim = sim or Sim(problem, dt)
     st = state or initial_state(problem)
     n = problem.steps if steps is None else steps
     rec = []
     g = sim.mat.Gc if Gc is None else Gc
     for k in range(n):
-        st = sim.step(st, Gc=g)
+        st = sim.step(st, Gc=g, solve=(k + 1) % n_sub == 0)
         if record_every and (k + 1) % record_every == 0:
             rec.append(st.numpy())
     return st, rec, sim
