@@ -121,7 +121,7 @@ typedef struct {
                                 after as many CG rounds as the handle's previous
                                 solve of the same kind needed (8 on the first
                                 solve), then every check_every rounds (the
-                                default path);
+                                default path); 1: after every round;
                                 0: enqueue exactly max_iter rounds and never
                                 synchronise (suitable for HIP-graph capture) */
     int32_t start;           /* damage solve only.  0: start from d_prev;
@@ -270,6 +270,20 @@ pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt
  * dt_out is a host array of n_instances doubles.
  */
 pf_status_t pf_cfl_dt(pf_mesh_t m, const pf_params_t* p, double factor, double* dt_out);
+
+/*
+ * Damage subcycling limit (Sec. 2.3, subcycling): the damage front moves at
+ * most ~0.6 c_R while the explicit step resolves c_p, so solving the damage
+ * sub-problem only every N_sub-th step is admissible for
+ *     N_sub <= N_max = floor(c_p / (0.6 c_R)),
+ * with c_p the plane's dilatational speed (as in pf_cfl_dt), c_s = sqrt(mu/rho)
+ * and c_R the Rayleigh speed of the same 2D medium (root of the Rayleigh
+ * equation).  Host outputs, one per instance: n_max_out (required) and the
+ * continuous ratio c_p / (0.6 c_R) in ratio_out (NULL allowed).  The
+ * subcycled schedule itself is the caller's: explicit steps every step (the
+ * history H advances every step), pf_damage_solve on every N_sub-th.
+ */
+pf_status_t pf_subcycle_limit(pf_mesh_t m, const pf_params_t* p, int32_t* n_max_out, double* ratio_out);
 
 /*
  * Tile-size autotuning (a set-up call, not part of the method; it allocates).

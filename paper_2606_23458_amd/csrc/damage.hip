@@ -692,6 +692,7 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
     // check_every rounds
     const int last = m->last_rounds[kind == CG_QP ? 0 : 1];
     int chunk = last > 0 ? std::min(last + 2, 64) : std::min(o->check_every, 8);
+    if (o->check_every == 1) chunk = 1;   // poll after every round: no round runs after the solve ends
     while (launched < max_rounds) {
       const int n = std::min(chunk, max_rounds - launched);
       for (int k = 0; k < n; ++k) round();

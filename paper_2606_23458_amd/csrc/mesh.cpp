@@ -697,6 +697,35 @@ extern "C" pf_status_t pf_cfl_dt(pf_mesh_t m, const pf_params_t* p, double facto
   return PF_OK;
 }
 
+extern "C" pf_status_t pf_subcycle_limit(pf_mesh_t m, const pf_params_t* p, int32_t* n_max_out, double* ratio_out) {
+  if (!m || !n_max_out) return fail(PF_ERR_ARG, "NULL argument");
+  pf_status_t st = check_params(m, p, nullptr, false);
+  if (st != PF_OK) return st;
+  for (int k = 0; k < m->n_inst; ++k) {
+    const pf_params_t& q = p[k];
+    const double mu = q.E / (2.0 * (1.0 + q.nu));
+    const double lam = (q.plane == PF_PLANE_STRESS) ? q.E * q.nu / (1.0 - q.nu * q.nu)
+                                                    : q.E * q.nu / ((1.0 + q.nu) * (1.0 - 2.0 * q.nu));
+    const double cp = std::sqrt((lam + 2.0 * mu) / q.rho);
+    const double cs = std::sqrt(mu / q.rho);
+    const double kap = (cs / cp) * (cs / cp);
+    // Rayleigh speed c_R = cs sqrt(eta): eta is the root in (0, 1) of the
+    // rationalised Rayleigh equation eta^3 - 8 eta^2 + (24 - 16 kap) eta - 16 (1 - kap) = 0
+    // (negative at 0, +1 at 1), found by bisection
+    auto g = [kap](double e) { return ((e - 8.0) * e + (24.0 - 16.0 * kap)) * e - 16.0 * (1.0 - kap); };
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-17; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      (g(mid) < 0.0 ? lo : hi) = mid;
+    }
+    const double cr = cs * std::sqrt(0.5 * (lo + hi));
+    const double ratio = cp / (0.6 * cr);
+    n_max_out[k] = int32_t(std::floor(ratio));
+    if (ratio_out) ratio_out[k] = ratio;
+  }
+  return PF_OK;
+}
+
 extern "C" pf_status_t pf_timer_enable(pf_mesh_t m, int32_t on) {
   if (!m) return fail(PF_ERR_ARG, "NULL handle");
   m->timing = on != 0;

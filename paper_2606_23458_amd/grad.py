@@ -35,6 +35,8 @@ class TrajectoryRunner:
     def __init__(self, sim: Simulator, steps: int, checkpoint_every: int = 50):
         if steps < 1 or checkpoint_every < 1:
             raise ValueError("steps and checkpoint_every must be >= 1")
+        if sim.n_sub != 1:
+            raise NotImplementedError("the reverse sweep differentiates the step with a damage solve (n_sub = 1)")
         self.sim = sim
         self.steps = steps
         self.K = checkpoint_every

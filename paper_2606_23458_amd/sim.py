@@ -196,7 +196,8 @@ class Simulator:
     """Staggered explicit phase-field simulation of one or more instances on one GPU."""
 
     def __init__(self, problems, dtype: str | None = None, tile_nodes: int | str = 0, cg: CgConfig | None = None,
-                 dt: list[float] | None = None, mesh: Mesh | None = None, cg_adj: CgConfig | None = None):
+                 dt: list[float] | None = None, mesh: Mesh | None = None, cg_adj: CgConfig | None = None,
+                 n_sub: int = 1, allow_beyond_limit: bool = False):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
@@ -218,6 +219,19 @@ class Simulator:
         else:
             for k, v in enumerate(dt):
                 self.dt[k] = float(v)
+        # damage subcycling (Sec. 2.3): the damage sub-problem is solved on
+        # every n_sub-th step; the pre-simulation check computes N_max
+        nmax = (C.c_int32 * n)()
+        ratio = (C.c_double * n)()
+        L.call("pf_subcycle_limit", self.mesh.handle, self.params, nmax, ratio)
+        self.n_max = [int(v) for v in nmax]
+        self.subcycle_ratio = [float(v) for v in ratio]
+        if int(n_sub) < 1:
+            raise ValueError("n_sub must be >= 1")
+        if int(n_sub) > min(self.n_max) and not allow_beyond_limit:
+            raise ValueError(f"n_sub = {n_sub} exceeds N_max = {min(self.n_max)} "
+                             f"(c_p / (0.6 c_R) = {min(self.subcycle_ratio):.3f})")
+        self.n_sub = int(n_sub)
         self.cg = cg or CgConfig(tol=default_tol(self.dtype_code))
         # adjoint solves stop relative to their right-hand side
         self.cg_adj = cg_adj or CgConfig(tol=default_tol(self.dtype_code))
@@ -271,11 +285,23 @@ class Simulator:
         self.explicit(s_in, s_out)
         self.damage(s_out.H, s_in.d, s_out.d, active_out, active_in)
 
+    def solves_at(self, step_index: int) -> bool:
+        """Whether step number step_index (0-based) solves the damage sub-problem."""
+        return (step_index + 1) % self.n_sub == 0
+
+    def skip_into(self, s_in: State, s_out: State) -> None:
+        """A step without the damage solve (subcycling): explicit step, then d_{n+1} = d_n."""
+        self.explicit(s_in, s_out)
+        s_out.d.copy_(s_in.d)
+
     def step(self, n: int = 1) -> State:
         for _ in range(n):
-            self.step_into(self.state, self._next, self._active_next, self.active)
+            if self.solves_at(self.steps_done):
+                self.step_into(self.state, self._next, self._active_next, self.active)
+                self.active, self._active_next = self._active_next, self.active
+            else:
+                self.skip_into(self.state, self._next)
             self.state, self._next = self._next, self.state
-            self.active, self._active_next = self._active_next, self.active
             self.steps_done += 1
         return self.state
 
@@ -301,15 +327,23 @@ class Simulator:
             snap = (self.state.clone(), self._next.d.clone(), self.active.clone())
             o = C.byref(CgConfig(self.cg.tol, self.cg.max_iter, 0, self.cg.start, self.cg.monotone,
                                  min(budget, self.cg.max_iter), 0).opts())
+            solved = []
             for k in range(w):
+                if not self.solves_at(self.steps_done + k):
+                    self.skip_into(self.state, self._next)
+                    self.state, self._next = self._next, self.state
+                    continue
                 self.explicit(self.state, self._next)
                 L.call("pf_damage_solve", self.mesh.handle, self.params, self._next.H.data_ptr(),
                        self.state.d.data_ptr(), self._next.d.data_ptr(), self.active.data_ptr(),
                        self._active_next.data_ptr(), o, self._win_stats[k].data_ptr(), _stream())
                 self.state, self._next = self._next, self.state
                 self.active, self._active_next = self._active_next, self.active
-            st = self._win_stats[:w].cpu().numpy().reshape(w, ni, 6)
-            if np.any(st[:, :, 3] != 0):
+                solved.append(k)
+            st = self._win_stats[:w].cpu().numpy().reshape(w, ni, 6)[solved]
+            if len(solved) == 0:
+                self.steps_done += w
+            elif np.any(st[:, :, 3] != 0):
                 # a solve did not finish within the budget: redo the window, polling
                 self.state, self._next, self.active, self._active_next = refs
                 self.state.copy_(snap[0])
@@ -318,7 +352,7 @@ class Simulator:
                 self.step(w)
                 budget = max(s["iters"] for s in self.cg_stats()) + 2 * margin
             else:
-                self.stats.copy_(self._win_stats[w - 1])
+                self.stats.copy_(self._win_stats[solved[-1]])
                 self.steps_done += w
                 budget = int(st[:, :, 0].max()) + margin
             done += w
@@ -357,6 +391,8 @@ class GraphStepper:
     """
 
     def __init__(self, sim: Simulator, rounds: int | None = None, more: int = 4):
+        if sim.n_sub != 1:
+            raise NotImplementedError("graph replay covers the step with a damage solve (n_sub = 1)")
         self.sim = sim
         base = sim.cg
         self.max_iter = base.max_iter
