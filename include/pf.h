@@ -265,6 +265,18 @@ pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt
                              pf_cg_stats_t* stats, pf_stream_t stream);
 
 /*
+ * Energy budget of a state, per instance and per unit thickness (the energy
+ * histories of Sec. 3, dynamic SENT; energies of Sec. 2.1-2.2):
+ *   E_kin  = 1/2 sum_i m_i |v_i|^2 with the lumped mass,
+ *   E_el   = sum_e A_e (g(d_e) psi+ + psi-),  d_e the element mean of d,
+ *   E_frac = Gc (d'Md/(2 l0) + l0/2 d'Kd) (AT2),
+ *            3 Gc/8 (int d / l0 + l0 d'Kd) (AT1).
+ * Reads s->{u, v, d}.  out: device double [n_instances][3] = (E_kin, E_el,
+ * E_frac); written on `stream` (sums in a fixed order, FP64).
+ */
+pf_status_t pf_energies(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out, pf_stream_t stream);
+
+/*
  * CFL time step of every instance (Sec. 2.3): dt_k = factor * h_min,k / c_p,k
  * with c_p = sqrt((lambda + 2 mu)/rho) and lambda of the instance's plane.
  * dt_out is a host array of n_instances doubles.

@@ -114,6 +114,8 @@ static void fill_instp(const pf_params_t& q, double dt, InstP<T>& o) {
   o.coef = T(s * s - c * c / 3.0);
   o.gamma = T(q.split == PF_SPLIT_STARCONVEX ? q.gamma_star : 0.0);
   o.eta = T(q.eta);
+  o.efr = T(q.model == PF_AT2 ? q.Gc / (2.0 * q.l0) : 3.0 * q.Gc / (8.0 * q.l0));
+  o.l0sq = T(q.l0 * q.l0);
   const double sc = q.l0 / q.Gc;   // the damage system is scaled by l0/Gc
   if (q.model == PF_AT2) {
     o.kap = T(q.l0 * q.l0);

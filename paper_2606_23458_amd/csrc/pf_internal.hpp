@@ -45,6 +45,9 @@ struct InstP {
   // d(scaled operator)/dGc terms for the adjoint, scaled by 1/Gc (see adjoint.hip)
   T gK, gM, gW;            // dL/dGc += -lam~'(gK K d + gM M d + gW w)
   T tol;
+  // fracture energy (per unit thickness): efr * (d'Md + l0sq d'Kd) for AT2
+  // (efr = Gc/(2 l0)), efr * (int d + l0sq d'Kd) for AT1 (efr = 3 Gc/(8 l0))
+  T efr, l0sq;
   int32_t model, bounds, split, pad;
 };
 

@@ -359,6 +359,15 @@ class Simulator:
         self._budget = budget
         return self.state
 
+    def energies(self, state: State | None = None) -> list[tuple[float, float, float]]:
+        """(E_kin, E_el, E_frac) of every instance, per unit thickness (pf_energies)."""
+        st = state or self.state
+        out = torch.empty(self.mesh.n_instances * 3, dtype=torch.float64, device=self.mesh.device)
+        ptrs = st.ptrs()
+        L.call("pf_energies", self.mesh.handle, self.params, C.byref(ptrs), out.data_ptr(), _stream())
+        e = out.cpu().numpy().reshape(-1, 3)
+        return [tuple(float(x) for x in r) for r in e]
+
     def cg_stats(self) -> list[dict]:
         raw = self.stats.cpu().numpy().view(np.int32).reshape(-1, 6)
         out = []
