@@ -4,7 +4,7 @@ The hot path (explicit step, damage solve, adjoint step) runs in hand-written
 HIP kernels for gfx950 in libpfrac.so; this package marshals arguments to it.
 """
 from . import _lib
-from .sim import CgConfig, GraphStepper, Mesh, Simulator, State, params_of
+from .sim import CgConfig, GraphStepper, Loading, Mesh, Simulator, State, params_of
 from .tune import tune_tiles
 
-__all__ = ["_lib", "CgConfig", "Mesh", "GraphStepper", "Simulator", "State", "params_of", "tune_tiles"]
+__all__ = ["_lib", "CgConfig", "Mesh", "GraphStepper", "Loading", "Simulator", "State", "params_of", "tune_tiles"]

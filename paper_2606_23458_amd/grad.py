@@ -77,6 +77,7 @@ class TrajectoryRunner:
             ck_state, ck_active, ck_dprev = self.checkpoints[sgi]
             states[0].copy_(ck_state)
             self.seg_active[0].copy_(ck_active)
+            self._k0 = k0
             self._recompute(k1 - k0, ck_dprev)
             cur, nxt = self._reverse(k1 - k0, cur, nxt, dGc)
         self.adj = [cur, nxt]
@@ -100,14 +101,14 @@ class TrajectoryRunner:
                              min(budget, sim.cg.max_iter), 0)
         for j in range(n):
             states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
-            sim.explicit(states[j], states[j + 1])
+            sim.explicit(states[j], states[j + 1], sim._loads(self._k0 + j, states[j]))
             sim.damage(states[j + 1].H, states[j].d, states[j + 1].d, act[j + 1], act[j], cg=o,
                        stats=stats[j])
         st = stats[:n].cpu().numpy().reshape(n, -1, 6)
         if np.any(st[:, :, 3] != 0):
             for j in range(n):
                 states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
-                sim.step_into(states[j], states[j + 1], act[j + 1], act[j])
+                sim.step_into(states[j], states[j + 1], act[j + 1], act[j], sim._loads(self._k0 + j, states[j]))
             self._fwd_budget = 0
         else:
             self._fwd_budget = int(st[:, :, 0].max()) + 4

@@ -192,6 +192,75 @@ def default_tol(dtype: str) -> float:
     return 1e-12 if dtype == "f64" else 1e-6
 
 
+def smooth_ramp(t: float, t_r: float) -> float:
+    """Load factor S(t) of the smooth traction ramp (Sec. 3, eq. smooth_traction_ramp)."""
+    if t <= 0.0:
+        return 0.0
+    if t >= t_r:
+        return 1.0
+    return 0.5 * (1.0 - np.cos(np.pi * t / t_r))
+
+
+def velocity_ramp(t: float, t_r: float) -> float:
+    """v(t)/v0 of the velocity ramp (Sec. 3, eq. kalthoff_velocity_ramp)."""
+    if t_r <= 0.0 or t >= t_r:
+        return 1.0
+    return max(t, 0.0) / t_r
+
+
+class Loading:
+    """Ramped boundary loads of a Simulator (Sec. 3 loading protocols).
+
+    traction: per instance an (N, 2) nodal force reached at full load (or
+    None), applied as f_ext = S(t_{n+1}) F in the explicit step that ends at
+    t_{n+1}; t_traction is the ramp time t_r of S.  t_velocity > 0 ramps the
+    prescribed velocities (the problems' v0 on their fixed DOFs) linearly up
+    to v0 over t_velocity, applied at each step's midpoint t_n + dt/2 (exact
+    displacement increments for the linear ramp).  The values are written into
+    the step's input arrays; every step of the method still runs in the
+    library's kernels.
+    """
+
+    def __init__(self, sim: "Simulator", traction=None, t_traction: float = 0.0, t_velocity: float = 0.0):
+        mesh = sim.mesh
+        self.sim = sim
+        self.t_traction = float(t_traction)
+        self.t_velocity = float(t_velocity)
+        dev = mesh.device
+        # instance of every internal node
+        inst = np.zeros(mesh.n_nodes, dtype=np.int64)
+        for k, inf in enumerate(mesh.info):
+            inst[inf.node_offset:inf.node_offset + inf.n_nodes] = k
+        self.node_inst = torch.tensor(inst, device=dev)
+        self.F = None
+        if traction is not None:
+            per = traction if isinstance(traction, (list, tuple)) else [traction]
+            F = mesh.nodes_to_internal([np.asarray(f, dtype=np.float64) for f in per]).T.copy()
+            self.F = torch.tensor(F, dtype=mesh.dtype, device=dev)            # (2, N)
+            self.f_ext = torch.empty_like(self.F)
+        if self.t_velocity > 0.0:
+            v0 = mesh.nodes_to_internal([np.asarray(p.v0, dtype=np.float64) for p in sim.problems]).T.copy()
+            fx = mesh.nodes_to_internal([np.asarray(p.fixed, dtype=np.float64) for p in sim.problems]).T.copy()
+            self.v0 = torch.tensor(v0, dtype=mesh.dtype, device=dev)
+            self.fixed = torch.tensor(fx > 0.5, device=dev)
+
+    def apply(self, step_index: int, s_in: "State"):
+        """Set the ramped prescribed velocities in s_in; return f_ext for the step (or None)."""
+        sim = self.sim
+        dts = np.asarray(list(sim.dt), dtype=np.float64)
+        if self.t_velocity > 0.0:
+            fac = torch.tensor([velocity_ramp((step_index + 0.5) * dt, self.t_velocity) for dt in dts],
+                               dtype=sim.mesh.dtype, device=sim.mesh.device)[self.node_inst]
+            v = s_in.nodes[2:4]
+            v.copy_(torch.where(self.fixed, self.v0 * fac, v))
+        if self.F is None:
+            return None
+        fac = torch.tensor([smooth_ramp((step_index + 1) * dt, self.t_traction) for dt in dts],
+                           dtype=sim.mesh.dtype, device=sim.mesh.device)[self.node_inst]
+        torch.mul(self.F, fac, out=self.f_ext)
+        return self.f_ext
+
+
 class Simulator:
     """Staggered explicit phase-field simulation of one or more instances on one GPU."""
 
@@ -241,6 +310,17 @@ class Simulator:
         self.state = self.initial_state()
         self._next = State(self.mesh)
         self.steps_done = 0
+        self.loading: Loading | None = None
+
+    def set_loading(self, traction=None, t_traction: float = 0.0, t_velocity: float = 0.0) -> None:
+        """Ramped loads for the following steps (see Loading); no arguments clears them."""
+        if traction is None and t_velocity <= 0.0:
+            self.loading = None
+        else:
+            self.loading = Loading(self, traction, t_traction, t_velocity)
+
+    def _loads(self, step_index: int, s_in: State):
+        return self.loading.apply(step_index, s_in) if self.loading is not None else None
 
     def set_Gc(self, values) -> None:
         for k, v in enumerate(np.atleast_1d(values)):
@@ -276,31 +356,33 @@ class Simulator:
                _ptr(guess), _ptr(active), C.byref(o), (stats if stats is not None else self.stats).data_ptr(),
                _stream())
 
-    def step_into(self, s_in: State, s_out: State, active_out: torch.Tensor, active_in: torch.Tensor | None) -> None:
+    def step_into(self, s_in: State, s_out: State, active_out: torch.Tensor, active_in: torch.Tensor | None,
+                  f_ext: torch.Tensor | None = None) -> None:
         """One staggered step s_in -> s_out; active_in are the flags of the solve that produced s_in.d.
 
         With the extrapolated start (cg.start = 1), s_out.d must hold the damage
         of the step before s_in on entry; the explicit step leaves it untouched.
         """
-        self.explicit(s_in, s_out)
+        self.explicit(s_in, s_out, f_ext)
         self.damage(s_out.H, s_in.d, s_out.d, active_out, active_in)
 
     def solves_at(self, step_index: int) -> bool:
         """Whether step number step_index (0-based) solves the damage sub-problem."""
         return (step_index + 1) % self.n_sub == 0
 
-    def skip_into(self, s_in: State, s_out: State) -> None:
+    def skip_into(self, s_in: State, s_out: State, f_ext: torch.Tensor | None = None) -> None:
         """A step without the damage solve (subcycling): explicit step, then d_{n+1} = d_n."""
-        self.explicit(s_in, s_out)
+        self.explicit(s_in, s_out, f_ext)
         s_out.d.copy_(s_in.d)
 
     def step(self, n: int = 1) -> State:
         for _ in range(n):
+            f = self._loads(self.steps_done, self.state)
             if self.solves_at(self.steps_done):
-                self.step_into(self.state, self._next, self._active_next, self.active)
+                self.step_into(self.state, self._next, self._active_next, self.active, f)
                 self.active, self._active_next = self._active_next, self.active
             else:
-                self.skip_into(self.state, self._next)
+                self.skip_into(self.state, self._next, f)
             self.state, self._next = self._next, self.state
             self.steps_done += 1
         return self.state
@@ -329,11 +411,12 @@ class Simulator:
                                  min(budget, self.cg.max_iter), 0).opts())
             solved = []
             for k in range(w):
+                f = self._loads(self.steps_done + k, self.state)
                 if not self.solves_at(self.steps_done + k):
-                    self.skip_into(self.state, self._next)
+                    self.skip_into(self.state, self._next, f)
                     self.state, self._next = self._next, self.state
                     continue
-                self.explicit(self.state, self._next)
+                self.explicit(self.state, self._next, f)
                 L.call("pf_damage_solve", self.mesh.handle, self.params, self._next.H.data_ptr(),
                        self.state.d.data_ptr(), self._next.d.data_ptr(), self.active.data_ptr(),
                        self._active_next.data_ptr(), o, self._win_stats[k].data_ptr(), _stream())
@@ -400,8 +483,9 @@ class GraphStepper:
     """
 
     def __init__(self, sim: Simulator, rounds: int | None = None, more: int = 4):
-        if sim.n_sub != 1:
-            raise NotImplementedError("graph replay covers the step with a damage solve (n_sub = 1)")
+        if sim.n_sub != 1 or sim.loading is not None:
+            raise NotImplementedError("graph replay covers the step with a damage solve (n_sub = 1), "
+                                      "without ramped loads")
         self.sim = sim
         base = sim.cg
         self.max_iter = base.max_iter
