@@ -41,10 +41,10 @@ def _pairs(mesh: Mesh):
     return rows, cols
 
 
-def stiffness_matrix(mesh: Mesh) -> sp.csr_matrix:
-    """K = sum_e A_e grad phi_k . grad phi_l (unit diffusion)."""
+def stiffness_matrix(mesh: Mesh, coef: np.ndarray | None = None) -> sp.csr_matrix:
+    """K = sum_e coef_e A_e grad phi_k . grad phi_l (coef = 1: unit diffusion)."""
     G = mesh.grad.numpy()
-    A = mesh.area.numpy()
+    A = mesh.area.numpy() if coef is None else mesh.area.numpy() * np.asarray(coef)
     ke = A[:, None, None] * np.einsum("ekc,elc->ekl", G, G)
     rows, cols = _pairs(mesh)
     n = mesh.n_nodes
@@ -81,15 +81,25 @@ def damage_coefficients(model: int, Gc: float, l0: float):
     raise ValueError(model)
 
 
-def assemble_damage(mesh: Mesh, H: np.ndarray, Gc: float, l0: float, model: int, K=None):
-    """Return (A, b) for the current history H (element array)."""
+def assemble_damage(mesh: Mesh, H: np.ndarray, Gc: float, l0: float, model: int, K=None, phi=None):
+    """Return (A, b) for the current history H (element array).
+
+    phi (element array, optional) makes the fracture energy a field,
+    Gc_e = Gc phi_e: every Gc in the element's weak form becomes Gc_e.
+    """
     H = np.asarray(H, dtype=np.float64)
     kappa, c0, b0 = damage_coefficients(model, Gc, l0)
-    if K is None:
-        K = stiffness_matrix(mesh)
-    A = (kappa * K + mass_matrix(mesh, c0 + 2.0 * H)).tocsr()
+    if phi is None:
+        if K is None:
+            K = stiffness_matrix(mesh)
+        A = (kappa * K + mass_matrix(mesh, c0 + 2.0 * H)).tocsr()
+        load = 2.0 * H + b0
+    else:
+        phi = np.asarray(phi, dtype=np.float64)
+        A = (stiffness_matrix(mesh, kappa * phi) + mass_matrix(mesh, c0 * phi + 2.0 * H)).tocsr()
+        load = 2.0 * H + b0 * phi
     b = np.zeros(mesh.n_nodes)
-    np.add.at(b, mesh.tri.numpy().ravel(), np.repeat((2.0 * H + b0) * mesh.area.numpy() / 3.0, 3))
+    np.add.at(b, mesh.tri.numpy().ravel(), np.repeat(load * mesh.area.numpy() / 3.0, 3))
     return A, b
 
 
@@ -190,17 +200,17 @@ class DamageQP:
         self.M = mass_matrix(self.mesh)
         self.w = node_area(self.mesh)
 
-    def system(self, H, Gc):
-        return assemble_damage(self.mesh, H, Gc, self.l0, self.model, K=self.K)
+    def system(self, H, Gc, phi=None):
+        return assemble_damage(self.mesh, H, Gc, self.l0, self.model, K=self.K, phi=phi)
 
-    def solve(self, H, Gc, d_prev):
+    def solve(self, H, Gc, d_prev, phi=None):
         """Return (d_new, lower, upper, x, A).
 
         Projected mode: d_new = x is the minimiser over d_prev <= d <= 1;
         lower / upper mark nodes held at d_prev / at 1.  Post-clamp mode: x is
         the unconstrained solution and d_new = min(max(x, d_prev), 1).
         """
-        A, b = self.system(H, Gc)
+        A, b = self.system(H, Gc, phi)
         if self.bounds == "projected":
             x, lo, up = solve_box_qp(A, b, d_prev, np.ones(len(b)), x0=d_prev)
             return x, lo, up, x, A
@@ -212,7 +222,7 @@ class DamageQP:
             return np.minimum(xc, 1.0), lo, up, x, A
         raise ValueError(self.bounds)
 
-    def tangent(self, A, x, act, upper, H, Gc, dH, dGc, dlb):
+    def tangent(self, A, x, act, upper, H, Gc, dH, dGc, dlb, phi=None, dphi=None):
         """Directional derivative of the update (implicit rule, Sec. 4.2).
 
         Projected mode: nodes held at d_prev follow it, nodes held at 1 do not
@@ -224,10 +234,16 @@ class DamageQP:
         kappa_dg = {2: self.l0, 1: 0.75 * self.l0}[self.model]
         b0_dg = {2: 0.0, 1: -3.0 / (8.0 * self.l0)}[self.model]
         c0_dg = {2: 1.0 / self.l0, 1: 0.0}[self.model]
-        Adot_x = dGc * (kappa_dg * (self.K @ x) + c0_dg * (self.M @ x)) + mass_matrix(self.mesh, 2.0 * dH) @ x
+        # tangent of the element fracture energies Gc_e = Gc phi_e
+        ne = self.mesh.n_elems
+        ph = np.ones(ne) if phi is None else np.asarray(phi, dtype=np.float64)
+        dph = np.zeros(ne) if dphi is None else np.asarray(dphi, dtype=np.float64)
+        dgce = dGc * ph + Gc * dph
+        Adot_x = (stiffness_matrix(self.mesh, kappa_dg * dgce) @ x
+                  + mass_matrix(self.mesh, c0_dg * dgce + 2.0 * dH) @ x)
         bdot = np.zeros(self.mesh.n_nodes)
         np.add.at(bdot, self.mesh.tri.numpy().ravel(),
-                  np.repeat((2.0 * dH + dGc * b0_dg) * self.mesh.area.numpy() / 3.0, 3))
+                  np.repeat((2.0 * dH + dgce * b0_dg) * self.mesh.area.numpy() / 3.0, 3))
         if self.bounds == "projected":
             held = act | upper
             free = ~held
@@ -241,21 +257,30 @@ class DamageQP:
         return np.where(upper, 0.0, xdot)
 
 
-def energies(mesh: Mesh, mass: np.ndarray, v, psi_total, d, Gc: float, l0: float, model: int, K=None, M=None):
+def energies(mesh: Mesh, mass: np.ndarray, v, psi_total, d, Gc: float, l0: float, model: int, K=None, M=None,
+             phi=None):
     """Kinetic, elastic and fracture energy per unit thickness.
 
     E_kin = 1/2 sum m_i |v_i|^2, E_el = sum_e A_e psi_e,
     E_frac(AT2) = Gc (d'Md/(2 l0) + l0/2 d'Kd),
-    E_frac(AT1) = 3Gc/8 (int d / l0 + l0 d'Kd).
+    E_frac(AT1) = 3Gc/8 (int d / l0 + l0 d'Kd);
+    with a field phi (Gc_e = Gc phi_e) each element's share is weighted by phi_e.
     """
     v = np.asarray(v)
     d = np.asarray(d)
-    K = stiffness_matrix(mesh) if K is None else K
     e_kin = 0.5 * float(np.sum(np.asarray(mass)[:, None] * v * v))
     e_el = float(np.sum(mesh.area.numpy() * np.asarray(psi_total)))
-    if model == 2:
+    if phi is not None:
+        K = stiffness_matrix(mesh, phi)
+        M = mass_matrix(mesh, phi)
+        w = np.zeros(mesh.n_nodes)
+        np.add.at(w, mesh.tri.numpy().ravel(), np.repeat(np.asarray(phi) * mesh.area.numpy() / 3.0, 3))
+    else:
+        K = stiffness_matrix(mesh) if K is None else K
         M = mass_matrix(mesh) if M is None else M
+        w = node_area(mesh)
+    if model == 2:
         e_fr = Gc * (float(d @ (M @ d)) / (2.0 * l0) + 0.5 * l0 * float(d @ (K @ d)))
     else:
-        e_fr = 3.0 * Gc / 8.0 * (float(node_area(mesh) @ d) / l0 + l0 * float(d @ (K @ d)))
+        e_fr = 3.0 * Gc / 8.0 * (float(w @ d) / l0 + l0 * float(d @ (K @ d)))
     return e_kin, e_el, e_fr

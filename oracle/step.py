@@ -18,6 +18,10 @@ three nodal values); H is one value per element; ties of the maximum keep
 H_n.  The gradient of the final-damage loss with respect to G_c is taken by
 forward-mode differentiation of the whole trajectory; the damage update
 contributes through the implicit rule (DamageQP.tangent).
+
+A spatially varying toughness (the per-element G_c(x) inverse problem named
+in Sec. 4) is G_c,e = G_c phi_e with a per-element factor phi (Sim.gc_scale);
+phi enters only the damage sub-problem and the fracture energy.
 """
 from __future__ import annotations
 
@@ -73,8 +77,11 @@ def initial_state(problem) -> State:
 class Sim:
     """Mesh, material and constant operators of one problem."""
 
-    def __init__(self, problem, dt: float | None = None, material: Material | None = None):
+    def __init__(self, problem, dt: float | None = None, material: Material | None = None, gc_scale=None):
         self.mat = material or Material.of(problem)
+        # per-element factor phi of G_c,e = G_c phi_e (None: uniform); a
+        # forward-mode dual tensor carries a direction of phi
+        self.gc_scale = gc_scale
         self.mesh: Mesh = make_mesh(problem.xy, problem.tri, problem.fixed)
         self.mass = lumped_mass(self.mesh, self.mat.rho)
         self.minv = 1.0 / self.mass
@@ -114,17 +121,25 @@ class Sim:
             gcv = float(gp)
         else:
             gt, gcv = None, float(Gc)
+        phi, pt = None, None
+        if self.gc_scale is not None:
+            if isinstance(self.gc_scale, torch.Tensor):
+                pp, pt = fwAD.unpack_dual(self.gc_scale)
+                phi = pp.detach().numpy()
+                pt = None if pt is None else pt.detach().numpy()
+            else:
+                phi = np.asarray(self.gc_scale, dtype=np.float64)
         Hn = Hp.detach().numpy()
-        dn, act, upper, x, A = self.qp.solve(Hn, gcv, lp.detach().numpy())
+        dn, act, upper, x, A = self.qp.solve(Hn, gcv, lp.detach().numpy(), phi)
         out = torch.from_numpy(dn)
-        if Ht is None and lt is None and gt is None:
+        if Ht is None and lt is None and gt is None and pt is None:
             return out, act, upper
         zero_e = np.zeros(self.mesh.n_elems)
         zero_n = np.zeros(self.mesh.n_nodes)
         tan = self.qp.tangent(A, x, act, upper, Hn, gcv,
                               zero_e if Ht is None else Ht.detach().numpy(),
                               0.0 if gt is None else float(gt),
-                              zero_n if lt is None else lt.detach().numpy())
+                              zero_n if lt is None else lt.detach().numpy(), phi, pt)
         return fwAD.make_dual(out, torch.from_numpy(tan)), act, upper
 
     def step(self, st: State, Gc=None, f_ext=None, info: dict | None = None, solve: bool = True) -> State:
@@ -144,8 +159,12 @@ class Sim:
         d = fwAD.unpack_dual(st.d)[0]
         psi_p, psi_m, g, _ = self.stress(u, d)
         psi = (g * psi_p + psi_m).detach().numpy()
+        phi = self.gc_scale
+        if isinstance(phi, torch.Tensor):
+            phi = fwAD.unpack_dual(phi)[0].detach().numpy()
         return energies(self.mesh, self.mass.numpy(), fwAD.unpack_dual(st.v)[0].detach().numpy(), psi,
-                        d.detach().numpy(), self.mat.Gc, self.mat.l0, self.mat.model, K=self.qp.K, M=self.qp.M)
+                        d.detach().numpy(), self.mat.Gc, self.mat.l0, self.mat.model, K=self.qp.K, M=self.qp.M,
+                        phi=phi)
 
 
 def explicit_step(problem, st: State, dt: float | None = None):
@@ -192,6 +211,31 @@ def loss_and_grad(problem, d_target: np.ndarray, Gc: float, steps: int | None = 
         st = initial_state(problem)
         for _ in range(n):
             st = sim.step(st, Gc=gc)
+        L = ((st.d - tgt) ** 2).mean()
+        Lp, Lt = fwAD.unpack_dual(L)
+        d_final = fwAD.unpack_dual(st.d)[0].detach().numpy().copy()
+    return float(Lp), (0.0 if Lt is None else float(Lt)), d_final
+
+
+def loss_and_field_derivative(problem, d_target: np.ndarray, Gc: float, gc_scale, direction,
+                              steps: int | None = None, dt: float | None = None):
+    """Loss of eq. inversion_loss for the toughness field G_c,e = G_c phi_e and its
+    directional derivative along a change `direction` of the element toughness
+    G_c,e (absolute units), by forward-mode differentiation of the trajectory.
+
+    The GPU adjoint's per-element gradient g_e = dL/dG_c,e satisfies
+    sum_e g_e direction_e = this derivative.
+    """
+    sim = Sim(problem, dt)
+    n = problem.steps if steps is None else steps
+    tgt = torch.as_tensor(np.asarray(d_target), dtype=torch.float64)
+    phi = torch.as_tensor(np.asarray(gc_scale, dtype=np.float64))
+    dphi = torch.as_tensor(np.asarray(direction, dtype=np.float64) / float(Gc))
+    with fwAD.dual_level():
+        sim.gc_scale = fwAD.make_dual(phi, dphi)
+        st = initial_state(problem)
+        for _ in range(n):
+            st = sim.step(st, Gc=float(Gc))
         L = ((st.d - tgt) ** 2).mean()
         Lp, Lt = fwAD.unpack_dual(L)
         d_final = fwAD.unpack_dual(st.d)[0].detach().numpy().copy()
