@@ -277,6 +277,30 @@ pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt
 pf_status_t pf_energies(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out, pf_stream_t stream);
 
 /*
+ * Spatially varying fracture toughness, Gc_e = Gc * phi_e per element (the
+ * per-element Gc(x) inverse problem that Sec. 4 names as the next step; each
+ * element's damage weak form, eq. damage_pde_at2 / damage_pde_at1, takes its
+ * own Gc_e, and so does its share of E_frac in pf_energies).  The element
+ * term of eq. implicit_gc_l0_element_term is then dL/dGc_e.
+ *   phi: device [n_elems_total] in the internal element order (as H), mesh
+ *        dtype, every value finite and > 0; copied into the handle, so the
+ *        caller may free it on return.  NULL restores a uniform Gc (phi = 1).
+ *   dgc_field: device double [n_elems_total] (internal order), caller-owned
+ *        and kept alive while the handle uses it, or NULL.  Every later
+ *        pf_step_backward adds dL/dGc_e to dgc_field[e] for each element e;
+ *        its per-instance dGc output is then sum_e phi_e dL/dGc_e (the
+ *        derivative along a common scaling of the field).
+ * The explicit step does not depend on Gc.  A set-up call: the first call
+ * with a field allocates n_te values of the mesh dtype in the handle; the
+ * field is read back to the host and checked (PF_ERR_ARG names the first bad
+ * element and leaves the previous field in place), and the call synchronises
+ * `stream`.  Work already enqueued on other streams must be ordered before
+ * this call by the caller; HIP graphs captured before the call are not
+ * updated (capture them again).
+ */
+pf_status_t pf_set_gc_field(pf_mesh_t m, const void* phi, double* dgc_field, pf_stream_t stream);
+
+/*
  * CFL time step of every instance (Sec. 2.3): dt_k = factor * h_min,k / c_p,k
  * with c_p = sqrt((lambda + 2 mu)/rho) and lambda of the instance's plane.
  * dt_out is a host array of n_instances doubles.

@@ -106,6 +106,7 @@ PROTOTYPES = {
     "pf_tune_tiles": [C.POINTER(MeshDesc), C.c_int32, C.c_int32, C.POINTER(Params), C.POINTER(TuneOpts),
                       C.POINTER(TuneResult), C.c_void_p],
     "pf_energies": [C.c_void_p, C.POINTER(Params), C.POINTER(StatePtrs), C.c_void_p, C.c_void_p],
+    "pf_set_gc_field": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "pf_subcycle_limit": [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
     "pf_timer_enable": [C.c_void_p, C.c_int32],
     "pf_timer_read": [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],

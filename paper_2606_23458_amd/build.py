@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpfrac.so")
-SOURCES = ["mesh.cpp", "explicit.hip", "damage.hip", "adjoint.hip", "energy.hip", "tune.cpp"]
+SOURCES = ["mesh.cpp", "explicit.hip", "damage.hip", "adjoint.hip", "energy.hip", "gcfield.hip", "tune.cpp"]
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
 

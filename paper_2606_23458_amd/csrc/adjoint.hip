@@ -6,6 +6,8 @@
 // min(d, 1) carry no adjoint); then
 //   dL/dGc  += -(1/Gc) lambda'(gK' K d + gM' M d + gW' w)      (AT2: the
 //              element term of eq. implicit_gc_l0_element_term; AT1 its analogue)
+//   With a toughness field Gc_e = Gc phi_e each element's term is dL/dGc_e
+//   (optionally accumulated per element) and dL/dGc sums phi_e dL/dGc_e.
 //   Hbar_e  += bH sum_k lambda_k A_e/3 - cH lambda' M^e d
 //   d_prev  :  nodes held at the bound get dbar_i - (A lambda)_i.
 // Explicit step: hand-written reverse mode of the corrector, the node gather,
@@ -39,7 +41,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T>* __restrict__ ip, double* part, const T* __restrict__ lam,
                                                        const T* __restrict__ dnp1, const T* __restrict__ Hnp1,
                                                        const T* __restrict__ dbar, const T* __restrict__ hbar_in,
-                                                       const uint8_t* __restrict__ W, T* hbar, T* dprev_bar) {
+                                                       const uint8_t* __restrict__ W, T* hbar, T* dprev_bar,
+                                                       double* dgc_field) {
   __shared__ double red[kWaves];
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
@@ -58,6 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
   __syncthreads();
   const T* __restrict__ geo = static_cast<const T*>(dm.geo);
   const size_t nte = size_t(dm.n_te);
+  const T* __restrict__ gcs = static_cast<const T*>(dm.gcs);
   double gsum = 0.0;
   for (int e = tid; e < t.n_telem; e += kBlock) {
     const int te = t.telem_begin + e;
@@ -70,8 +74,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
     const T glx = g0x * l0v + g1x * l1v + g2x * l2v;
     const T gly = g0y * l0v + g1y * l1v + g2y * l2v;
     const T ls = l0v + l1v + l2v;
-    const T kA = P.kap * A;
-    const T mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
+    const T ph = gcs ? gcs[te] : T(1);
+    const T kA = P.kap * ph * A;
+    const T mA = (P.c0 * ph + P.cH * He) * A * T(1.0 / 12.0);
     qc[3 * e + 0] = kA * (g0x * glx + g0y * gly) + mA * (l0v + ls);
     qc[3 * e + 1] = kA * (g1x * glx + g1y * gly) + mA * (l1v + ls);
     qc[3 * e + 2] = kA * (g2x * glx + g2y * gly) + mA * (l2v + ls);
@@ -85,7 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
                          (double(l0v) * double(d0) + double(l1v) * double(d1) + double(l2v) * double(d2) +
                           double(ls) * double(ds));
       const double lw = double(A) / 3.0 * double(ls);
-      gsum -= double(P.gK) * lKd + double(P.gM) * lMd + double(P.gW) * lw;
+      // dL/dGc_e of this element; the instance's Gc scales every Gc_e by phi_e
+      const double ge = -(double(P.gK) * lKd + double(P.gM) * lMd + double(P.gW) * lw);
+      gsum += gcs ? double(ph) * ge : ge;
+      if (dgc_field) dgc_field[gid] += ge;
       hbar[gid] = hbar_in[gid] + T(double(P.bH) * lw - double(P.cH) * lMd);
     }
   }
@@ -230,7 +238,7 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   hipLaunchKernelGGL(k_adj_damage<T>, grid, block, lds_d, s, m->dm, ip, m->dw.part, lam,
                      static_cast<const T*>(s_np1->d), static_cast<const T*>(s_np1->H),
                      static_cast<const T*>(adj1->d), static_cast<const T*>(adj1->H), m->dw.wset,
-                     static_cast<T*>(m->dw.hbar), static_cast<T*>(adj0->d));
+                     static_cast<T*>(m->dw.hbar), static_cast<T*>(adj0->d), m->dgc_field);
   hipLaunchKernelGGL(k_adj_reduce, dim3(m->n_inst), block, 0, s, m->dw.ctl, m->dw.part, m->n_tiles, dGc);
   const StateIn<T> sn = state_in<T>(s_n), sn1 = state_in<T>(s_np1), a1 = state_in<T>(adj1);
   const StateOut<T> a0 = state_out<T>(adj0);

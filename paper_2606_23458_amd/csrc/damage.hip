@@ -247,6 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   // chunk in its fixed corner order.
   const T* __restrict__ geo = static_cast<const T*>(a.dm.geo);
   const size_t nte = size_t(a.dm.n_te);
+  // per-element toughness factor phi_e (Gc_e = Gc phi_e) scales every Gc
+  // term of the element's operator and load; absent, phi_e = 1 exactly
+  const T* __restrict__ gcs = static_cast<const T*>(a.dm.gcs);
   if (setup) {
     T dacc[NPT], bacc[NPT];
 #pragma unroll
@@ -262,15 +265,16 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
         const int te = t.telem_begin + e;
         const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
         const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-        const T kA = P.kap * A;
+        const T ph = gcs ? gcs[te] : T(1);
+        const T kA = P.kap * ph * A;
         const T He = a.H[a.dm.te_gid[te]];
-        const T mA = (P.c0 + P.cH * He) * A * T(1.0 / 12.0);
+        const T mA = (P.c0 * ph + P.cH * He) * A * T(1.0 / 12.0);
         a.mte[te] = mA;
         const int l = e - e0;
         dc[3 * l + 0] = kA * (g0x * g0x + g0y * g0y) + T(2) * mA;
         dc[3 * l + 1] = kA * (g1x * g1x + g1y * g1y) + T(2) * mA;
         dc[3 * l + 2] = kA * (g2x * g2x + g2y * g2y) + T(2) * mA;
-        bc[3 * chs + l] = qp ? (P.b0 + P.bH * He) * A * T(1.0 / 3.0) : T(0);
+        bc[3 * chs + l] = qp ? (P.b0 * ph + P.bH * He) * A * T(1.0 / 3.0) : T(0);
       }
       __syncthreads();
 #pragma unroll
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
         const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
         const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
         const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-        const T kA = P.kap * A;
+        const T kA = P.kap * (gcs ? gcs[te] : T(1)) * A;
         const T mA = a.mte[te];
         const double s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
         const double gpx = double(g0x) * s0 + double(g1x) * s1 + double(g2x) * s2;
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
       const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
       const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-      const T kA = P.kap * A;
+      const T kA = P.kap * (gcs ? gcs[te] : T(1)) * A;
       const T mA = a.mte[te];
       const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
       const T gpx = g0x * s0 + g1x * s1 + g2x * s2;

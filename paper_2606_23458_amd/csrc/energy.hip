@@ -4,6 +4,7 @@
 //   E_el   = sum_e A_e (g(d_e) psi+(eps_e) + psi-(eps_e)),   d_e = mean of the element's nodal d
 //   E_frac = Gc/(2 l0) d'Md + Gc l0/2 d'Kd               (AT2)
 //          = 3 Gc/(8 l0) (int d + l0^2 d'Kd)             (AT1)
+// (with a toughness field each element's share takes its own Gc_e)
 // psi- comes from the split's stress: every split's psi+- is homogeneous of
 // degree 2 in the strain, so psi- = sigma-:eps / 2.
 //
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(DevMesh dm, const InstP<T>* _
   const T* __restrict__ geo = static_cast<const T*>(dm.geo);
   const size_t nte = size_t(dm.n_te);
   const bool at2 = P.model == PF_AT2;
+  const T* __restrict__ gcs = static_cast<const T*>(dm.gcs);
   for (int e = tid; e < t.n_own_elem; e += kBlock) {
     const int te = t.telem_begin + e;
     const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
@@ -67,7 +69,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(DevMesh dm, const InstP<T>* _
     const double gy = double(g0y) * d0 + double(g1y) * d1 + double(g2y) * d2;
     const double dkd = double(A) * (gx * gx + gy * gy);
     const double first = at2 ? double(A) * (d0 * d0 + d1 * d1 + d2 * d2 + ds * ds) / 12.0 : double(A) * ds / 3.0;
-    ef += double(P.efr) * (first + double(P.l0sq) * dkd);
+    const double fe = double(P.efr) * (first + double(P.l0sq) * dkd);
+    ef += gcs ? double(gcs[te]) * fe : fe;   // Gc_e = Gc phi_e
   }
   double v[3] = {ek, ee, ef};
   block_reduce_to0<3, 0u>(v, red);

@@ -88,6 +88,8 @@ struct DevMesh {
   const void* inv_w;            // [N] 1 / sum_{e ni i} A_e/3 (mesh dtype)
   const void* wlump;            // [N] sum_{e ni i} A_e/3 (mesh dtype)
   const uint8_t* fixed;         // [N] bit0 x prescribed, bit1 y prescribed
+  const void* gcs;              // [n_te] toughness factor phi_e = Gc_e / Gc of each tile element
+                                // (mesh dtype), or null for a uniform Gc
   int32_t n_nodes, n_elems, n_tiles, n_te;
 };
 
@@ -141,6 +143,8 @@ struct pf_mesh_s {
   hipEvent_t poll_ev = nullptr;      // marks the copy of the control blocks (convergence polls)
   bool timing = false;
   pf::Timer timers[5];
+  void* gcs_buf = nullptr;           // device storage of dm.gcs (allocated by the first pf_set_gc_field)
+  double* dgc_field = nullptr;       // caller's per-element dL/dGc_e accumulator, or null
 };
 
 namespace pf {

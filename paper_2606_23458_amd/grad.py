@@ -61,8 +61,22 @@ class TrajectoryRunner:
                 self.checkpoints.append((sim.state.clone(), sim.active.clone(), sim._next.d.clone()))
         return sim.state
 
-    def backward(self, d_bar: torch.Tensor) -> torch.Tensor:
-        """Reverse sweep from the adjoint of the final damage; returns dL/dGc per instance (float64)."""
+    def backward(self, d_bar: torch.Tensor, field_grad: torch.Tensor | None = None) -> torch.Tensor:
+        """Reverse sweep from the adjoint of the final damage; returns dL/dGc per instance (float64).
+
+        field_grad (float64 device [n_elems], internal order) also receives
+        dL/dGc_e of every element (the toughness field Gc_e = Gc phi_e)."""
+        mesh = self.sim.mesh
+        if field_grad is None:
+            return self._backward(d_bar)
+        held = mesh.gc_grad
+        mesh.set_gc_field(mesh.gc_scale, field_grad)
+        try:
+            return self._backward(d_bar)
+        finally:
+            mesh.set_gc_field(mesh.gc_scale, held)
+
+    def _backward(self, d_bar: torch.Tensor) -> torch.Tensor:
         sim = self.sim
         mesh = sim.mesh
         dGc = torch.zeros(mesh.n_instances, dtype=torch.float64, device=mesh.device)
@@ -162,3 +176,17 @@ def loss_and_grad(sim: Simulator, Gc, target: torch.Tensor, steps: int, checkpoi
     L_ = instance_mse(sim.mesh, d, target)
     L_.sum().backward()
     return L_.detach().cpu().numpy(), g.grad.detach().cpu().numpy()
+
+
+def field_loss_and_grad(sim: Simulator, target: torch.Tensor, steps: int, checkpoint_every: int = 50,
+                        runner: TrajectoryRunner | None = None):
+    """Per-instance loss (eq. inversion_loss) and its gradient with respect to every
+    element's toughness Gc_e = Gc phi_e at the simulator's current field (one
+    float64 array per instance, user element order)."""
+    runner = runner or TrajectoryRunner(sim, steps, checkpoint_every)
+    d = runner.forward().d.double().clone().requires_grad_(True)
+    L_ = instance_mse(sim.mesh, d, target)
+    L_.sum().backward()
+    g = torch.zeros(sim.mesh.n_elems, dtype=torch.float64, device=sim.mesh.device)
+    runner.backward(d.grad.to(sim.mesh.dtype).contiguous(), field_grad=g)
+    return L_.detach().cpu().numpy(), sim.mesh.elems_from_internal(g)

@@ -82,6 +82,26 @@ class Mesh:
             pos = np.empty(m, dtype=np.int64)
             pos[self.elem_perm[o:o + m]] = np.arange(o, o + m)
             self.elem_pos.append(pos)
+        # toughness field Gc_e = Gc phi_e held by the handle (pf_set_gc_field)
+        self.gc_scale: torch.Tensor | None = None
+        self.gc_grad: torch.Tensor | None = None
+        self.gc_version = 0
+
+    def set_gc_field(self, scale: torch.Tensor | None, grad: torch.Tensor | None = None) -> None:
+        """phi_e in internal element order (mesh dtype, device) or None for a uniform Gc;
+        grad: float64 device tensor [n_elems] that pf_step_backward accumulates dL/dGc_e into."""
+        same = scale is not None and scale is self.gc_scale   # re-registering the held field
+        if scale is not None and not same:
+            scale = scale.to(device=self.device, dtype=self.dtype).clone().contiguous()
+            if scale.shape != (self.n_elems,):
+                raise ValueError(f"toughness field must have {self.n_elems} values")
+        if grad is not None and (grad.dtype != torch.float64 or grad.shape != (self.n_elems,)
+                                 or grad.device.type != self.device.type or not grad.is_contiguous()):
+            raise ValueError("grad must be a contiguous float64 device tensor of n_elems values")
+        L.call("pf_set_gc_field", self.handle, _ptr(scale), _ptr(grad), _stream())
+        if not same and (scale is not None or self.gc_scale is not None):
+            self.gc_version += 1
+        self.gc_scale, self.gc_grad = scale, grad
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -326,6 +346,18 @@ class Simulator:
         for k, v in enumerate(np.atleast_1d(values)):
             self.params[k].Gc = float(v)
 
+    def set_gc_field(self, fields=None) -> None:
+        """Spatially varying toughness Gc_e = Gc phi_e: one array of phi_e per
+        instance in the user's element order (None: uniform Gc)."""
+        if fields is None:
+            self.mesh.set_gc_field(None, self.mesh.gc_grad)
+            return
+        if len(fields) != self.mesh.n_instances:
+            raise ValueError("one toughness field per instance")
+        phi = torch.tensor(self.mesh.elems_to_internal([np.asarray(f, dtype=np.float64) for f in fields]),
+                           dtype=self.mesh.dtype, device=self.mesh.device)
+        self.mesh.set_gc_field(phi, self.mesh.gc_grad)
+
     def initial_state(self) -> State:
         return State.from_user(self.mesh, [{"u": p.u0, "v": p.v0, "a": p.a0, "d": p.d0, "H": p.H0}
                                            for p in self.problems])
@@ -478,8 +510,8 @@ class GraphStepper:
     second graph `more` further rounds (resume).  A step replays the first
     graph, reads the per-instance CG statistics once, and replays the second
     until every instance has finished, so results equal Simulator.step bit for
-    bit.  The material parameters and time steps are those of the capture;
-    build a new stepper after changing them.
+    bit.  The material parameters, toughness field and time steps are those
+    of the capture; build a new stepper after changing them.
     """
 
     def __init__(self, sim: Simulator, rounds: int | None = None, more: int = 4):
@@ -501,6 +533,7 @@ class GraphStepper:
         cont = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, more, 1)
         self._params = bytes(sim.params)
         self._dt = list(sim.dt)
+        self._gc_version = sim.mesh.gc_version
         self.states = (sim.state, sim._next)
         self.actives = (sim.active, sim._active_next)
         self.graphs = []
@@ -519,7 +552,8 @@ class GraphStepper:
 
     def step(self, n: int = 1) -> State:
         sim = self.sim
-        if bytes(sim.params) != self._params or list(sim.dt) != self._dt:
+        if bytes(sim.params) != self._params or list(sim.dt) != self._dt \
+                or sim.mesh.gc_version != self._gc_version:
             raise RuntimeError("parameters changed since the graphs were captured")
         for _ in range(n):
             g1, g2 = self.graphs[self.parity]
