@@ -202,6 +202,66 @@ def subcycling(steps: int) -> dict:
     return out
 
 
+def gc_field(steps: int) -> dict:
+    """Toughness field Gc_e = Gc phi_e (phi ~ U[0.5, 1.5] per element) on the 1024x512 plate against a
+    uniform Gc, and the per-element gradient's reverse sweep against the scalar one (256x128, FP64)."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import Simulator
+    from paper_2606_23458_amd.grad import TrajectoryRunner
+    p = w.config1()
+    phi = np.random.default_rng(17).uniform(0.5, 1.5, p.n_elems)
+    a = Simulator(p, dtype="f32")
+    b = Simulator(p, dtype="f32", dt=list(a.dt))
+    b.set_gc_field([phi])
+    out = {}
+    for key, sim in (("uniform", a), ("field", b)):
+        sim.run(20)
+        gpu_sync()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        sim.run(steps)
+        ev1.record()
+        gpu_sync()
+        out[key + "_ms_per_step"] = round(ev0.elapsed_time(ev1) / steps, 4)
+        out[key + "_elem_steps_per_s"] = round(p.n_elems * steps / (ev0.elapsed_time(ev1) / 1e3), 1)
+    p3 = w.config3().with_(steps=100)
+    phi3 = np.random.default_rng(18).uniform(0.5, 1.5, p3.n_elems)
+    sim = Simulator(p3, dtype="f64")
+    sim.set_gc_field([phi3])
+    run = TrajectoryRunner(sim, steps=100, checkpoint_every=25)
+    run.forward()
+    dbar = (sim.state.d * (2.0 / sim.mesh.n_nodes)).contiguous()
+    ge = torch.zeros(sim.mesh.n_elems, dtype=torch.float64, device="cuda")
+    times = {}
+    for key, fg in (("scalar", None), ("per_element", ge)):
+        gpu_sync()
+        t0 = time.perf_counter()
+        run.backward(dbar, field_grad=fg)
+        gpu_sync()
+        times[key] = time.perf_counter() - t0
+    out["bwd_workload"] = "256x128 plate, FP64, 100 steps, checkpoint every 25"
+    out["bwd_scalar_s"] = round(times["scalar"], 3)
+    out["bwd_per_element_s"] = round(times["per_element"], 3)
+    return out
+
+
+def energies_cost(reps: int = 50) -> dict:
+    """pf_energies on the 1024x512 plate: time per call."""
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import Simulator
+    sim = Simulator(w.config1(), dtype="f32")
+    sim.run(50)
+    gpu_sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.energies()
+    gpu_sync()
+    return {"us_per_call_incl_readback": round((time.perf_counter() - t0) / reps * 1e6, 1)}
+
+
 def roofline(res, w: int) -> dict:
     ne = res["ne"]
     fam = res["fam"]
@@ -335,6 +395,7 @@ def main():
         torch.cuda.synchronize()
         del a, c
     res = run_headline(args.steps, args.warmup, args.tile_nodes)
+    print("[bench] headline done", file=sys.stderr, flush=True)
     ms_step = res["ms"] / args.steps
     value = res["ne"] * args.steps / (res["ms"] / 1e3)
     iters = res["iters"]
@@ -355,11 +416,13 @@ def main():
     }
     if not args.no_extras:
         for key, fn in (("bwd_fwd", bwd_fwd_ratio), ("batched", batched_vs_plain),
-                        ("subcycling", lambda: subcycling(100))):
+                        ("subcycling", lambda: subcycling(100)), ("gc_field", lambda: gc_field(100)),
+                        ("energies", energies_cost)):
             try:
                 out[key] = fn()
             except Exception as e:   # reported on the line; the headline stands on its own
                 out[key] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"[bench] {key} done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
