@@ -147,6 +147,16 @@ typedef struct {
                                 and resume, a step can be captured once as a
                                 HIP graph of a fixed number of rounds and
                                 continued, rarely, by a second graph. */
+    int32_t precond;         /* preconditioner of the CG runs.  0 or 1: Jacobi
+                                (M = D^-1 on the free nodes).  2, 3 or 4: the
+                                Chebyshev-Jacobi polynomial of that degree,
+                                M = p(D^-1 A) D^-1, on the interval
+                                [lmax/10, lmax] where lmax is a Gershgorin
+                                bound of D^-1 A taken at set-up (so M is SPD);
+                                a round then makes `precond` matrix-vector
+                                products and one reduction, and max_iter and
+                                the iteration counts of pf_cg_stats_t count
+                                rounds.  Damage solve and adjoint alike. */
 } pf_cg_opts_t;
 
 /* Per-instance solve statistics, written to DEVICE memory by the solve. */

@@ -43,7 +43,7 @@ class StatePtrs(C.Structure):
 
 class CgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32), ("start", C.c_int32),
-                ("monotone", C.c_int32), ("rounds", C.c_int32), ("resume", C.c_int32)]
+                ("monotone", C.c_int32), ("rounds", C.c_int32), ("resume", C.c_int32), ("precond", C.c_int32)]
 
 
 class CgStats(C.Structure):

@@ -281,6 +281,7 @@ extern "C" pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const
   if ((st = check_state(adj_n, true, true, "adj_n")) != PF_OK) return st;
   if (!active_np1 || !dGc || !opts) return fail(PF_ERR_ARG, "NULL argument");
   if (!(opts->tol > 0) || opts->max_iter < 1) return fail(PF_ERR_ARG, "need tol > 0 and max_iter >= 1");
+  if (opts->precond < 0 || opts->precond > 4) return fail(PF_ERR_ARG, "precond must be in [0, 4]");
   if (states_share(adj_n, adj_np1) || states_share(adj_n, s_n) || states_share(adj_n, s_np1))
     return fail(PF_ERR_ARG, "adj_n shares an array with an input");
   const size_t w = elem_size(m->dtype);

@@ -92,7 +92,45 @@ struct DmgArgs {
   int32_t max_iter;
   int32_t kind;        // CG_QP or CG_LINEAR
   int32_t start;       // 1: extrapolated start for the damage solve
+  // Chebyshev-Jacobi preconditioner (degree cheb >= 2)
+  T* zb;               // z = M r of the current iteration (written by the A z pass)
+  T* y0; T* y1;        // Chebyshev iterate pair
+  T* dv;               // Chebyshev update direction (owner only)
+  int32_t cheb;        // polynomial degree
+  int32_t stage;       // pass within a round: 0 main pass, 1 .. cheb-2 Chebyshev steps, cheb-1 the A z pass
 };
+
+// Chebyshev-Jacobi preconditioner z = p(D^-1 A) D^-1 r: `cheb` steps of the
+// Chebyshev iteration for A y = r from y = 0 with Jacobi scaling on the
+// interval [lmax/kChebRatio, lmax] (Saad, Iterative Methods for Sparse Linear
+// Systems, Sec. 12.3): with theta, delta the centre and half-width of the
+// interval, sigma = theta/delta, rho_0 = 1/sigma,
+//   y_1 = D^-1 r / theta,  d_0 = y_1,
+//   rho_j = 1/(2 sigma - rho_{j-1}),
+//   d_j = rho_j rho_{j-1} d_{j-1} + (2 rho_j/delta) D^-1 (r - A y_j),  y_{j+1} = y_j + d_j.
+// Every eigenvalue of D^-1 A lies in (0, lmax] (lmax a Gershgorin bound), where
+// the polynomial is positive, so M is symmetric positive definite and CG
+// applies unchanged.
+constexpr double kChebRatio = 10.0;
+
+struct ChebCoef {
+  double inv_theta, c1, c2;   // 1/theta; c1, c2 of step j: d_j = c1 d_{j-1} + c2 D^-1 res
+};
+
+__device__ __forceinline__ ChebCoef cheb_coef(double lmax, int j) {
+  const double b = fmax(lmax, 1.0), a = b / kChebRatio;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+  double rp = 1.0 / sigma, rj = rp;
+  for (int i = 1; i <= j; ++i) {
+    rp = rj;
+    rj = 1.0 / (2.0 * sigma - rp);
+  }
+  ChebCoef c;
+  c.inv_theta = 1.0 / theta;
+  c.c1 = rj * rp;
+  c.c2 = 2.0 * rj / delta;
+  return c;
+}
 
 __global__ void k_dmg_init(Ctl* ctl, int n_inst, int kind, int monotone) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,7 +163,7 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
   return v < lo ? lo : (v > T(1) ? T(1) : v);
 }
 
-template <typename T, int NPT>
+template <typename T, int NPT, bool CHEB>
 __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[8 * kWaves];
   const int tile = tile_of_block(a.dm.n_tiles);
@@ -133,6 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   const Ctl* c = a.ctl + t.inst;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
+  // Chebyshev steps and the A z pass follow the main pass of first / iterate rounds only
+  const int stage = CHEB ? a.stage : 0;
+  if (CHEB && stage > 0 && (mode == MODE_RESTART || mode == MODE_CHECK)) return;
   const InstP<T> P = a.ip[t.inst];
   const bool qp = (a.kind == CG_QP);
   const bool projected = qp && (P.bounds == PF_BOUNDS_PROJECTED);
@@ -179,13 +220,21 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
 
   stage_corners(a.dm, t, coffs, clist);
 
+  // Chebyshev coefficients of this pass's step (the main pass makes step 1)
+  ChebCoef chc{1.0, 0.0, 0.0};
+  if (CHEB) chc = cheb_coef(c->lmax, stage + 1);
+  const T ith = T(chc.inv_theta);
+  const T* __restrict__ ysrc = ((stage - 1) & 1) ? a.y1 : a.y0;   // y_j read by stage j-1 >= 1
+
   // ---- phase 1: the vector to multiply, on owned and halo nodes -------------
   double amin = INFINITY, ch = 0.0;
   for (int i = tid; i < nloc; i += kBlock) {
     const bool own = i < t.n_own;
     const int g = own ? t.node_begin + i : a.dm.halo_idx[t.halo_begin + (i - t.n_own)];
     T v;
-    if (setup && qp) {
+    if (CHEB && stage > 0) {
+      v = ysrc[g];   // the Chebyshev iterate of the previous pass (0 on held nodes)
+    } else if (setup && qp) {
       // start at d_prev (or its extrapolation in time), or at 1 where the guess
       // holds the node at the upper bound
       const T lbv = a.lb[g];
@@ -208,16 +257,18 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
         v = clamp01<T>(xh + T(kExpandStep) * a.dinv[g] * rh, a.lb[g]);
       }
     } else if (!iter) {
-      v = Wc[g] ? T(0) : a.dinv[g] * rc[g];    // first pass of a CG run: z = M r
+      // first pass of a CG run: z = M r (Jacobi), or y_1 = D^-1 r / theta (Chebyshev)
+      v = Wc[g] ? T(0) : (CHEB ? a.dinv[g] * rc[g] * ith : a.dinv[g] * rc[g]);
     } else {
       const uint8_t wf = Wc[g];
       const T di = a.dinv[g];
       const T rv = rc[g];
       const T sn = (beta == 0.0) ? wc[g] : wc[g] + be * sc[g];   // s = A p of this iteration
       const T rn = rv - al * sn;
-      v = wf ? T(0) : di * rn;                                   // z of the next iteration
+      // z of the next iteration (Jacobi), or the first Chebyshev iterate y_1
+      v = wf ? T(0) : (CHEB ? di * rn * ith : di * rn);
       if (own) {
-        const T zv = wf ? T(0) : di * rv;
+        const T zv = wf ? T(0) : (CHEB ? a.zb[g] : di * rv);
         const T pv = (beta == 0.0) ? zv : zv + be * a.p[g];
         const T xv = xc[g];
         T xn = xv + al * pv;
@@ -251,13 +302,17 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   // term of the element's operator and load; absent, phi_e = 1 exactly
   const T* __restrict__ gcs = static_cast<const T*>(a.dm.gcs);
   if (setup) {
-    T dacc[NPT], bacc[NPT];
+    T dacc[NPT], bacc[NPT], sacc[NPT];
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) dacc[r] = T(0), bacc[r] = T(0);
+    for (int r = 0; r < NPT; ++r) dacc[r] = T(0), bacc[r] = T(0), sacc[r] = T(0);
     // two chunks: 4 values of width w per element in two halves fit the 3
     // values per element of an iteration pass (chunk sizes depend only on the
-    // tile, so the sums are the same in a batched and a single-instance handle)
-    const int chs = (t.n_telem + 1) / 2;
+    // tile, so the sums are the same in a batched and a single-instance handle;
+    // chunks split each node's corner sequence without reordering it).  The
+    // Chebyshev preconditioner also needs the absolute row sums of the element
+    // matrices (7 values per element): four chunks.
+    const int chs = CHEB ? (t.n_telem + 3) / 4 : (t.n_telem + 1) / 2;
+    T* sc_ = dc + 4 * chs;   // [3 chunk] absolute row sums per corner (Chebyshev)
     for (int e0 = 0; e0 < t.n_telem; e0 += chs) {
       const int e1 = min(e0 + chs, t.n_telem);
       __syncthreads();
@@ -275,6 +330,15 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
         dc[3 * l + 1] = kA * (g1x * g1x + g1y * g1y) + T(2) * mA;
         dc[3 * l + 2] = kA * (g2x * g2x + g2y * g2y) + T(2) * mA;
         bc[3 * chs + l] = qp ? (P.b0 * ph + P.bH * He) * A * T(1.0 / 3.0) : T(0);
+        if (CHEB) {
+          // off-diagonal entries kA grad phi_k . grad phi_l + mA of the element matrix
+          const T o01 = fabs(kA * (g0x * g1x + g0y * g1y) + mA);
+          const T o02 = fabs(kA * (g0x * g2x + g0y * g2y) + mA);
+          const T o12 = fabs(kA * (g1x * g2x + g1y * g2y) + mA);
+          sc_[3 * l + 0] = dc[3 * l + 0] + o01 + o02;
+          sc_[3 * l + 1] = dc[3 * l + 1] + o01 + o12;
+          sc_[3 * l + 2] = dc[3 * l + 2] + o02 + o12;
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -288,6 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
             if (e >= e0 && e < e1) {
               dacc[r] += dc[cc - 3 * e0];
               bacc[r] += bc[3 * chs + e - e0];
+              if (CHEB) sacc[r] += sc_[cc - 3 * e0];
             }
           }
         }
@@ -300,6 +365,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
         const int g = t.node_begin + i;
         if (qp) a.b[g] = bacc[r];
         a.dinv[g] = T(1) / dacc[r];
+        // Gershgorin bound of D^-1 A, carried to the reduction as -max in the
+        // min-combined slot (unused by restart passes)
+        if (CHEB) amin = fmin(amin, -double(sacc[r]) / double(dacc[r]));
       }
     }
   }
@@ -419,12 +487,41 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     __syncthreads();
     T* wn = iter ? wn_ : (cur1 ? a.w1 : a.w0);
     const T* rz = iter ? rn_ : rc;
+    T* ydst = (stage & 1) ? a.y1 : a.y0;
     for (int i = tid; i < t.n_own; i += kBlock) {
       const int g = t.node_begin + i;
       const int j0 = coffs[i], j1 = coffs[i + 1];
       T qi = T(0);
       for (int j = j0; j < j1; ++j) qi += qc[clist[j]];
+      if (CHEB && stage < a.cheb - 1) {
+        // Chebyshev step stage + 1: qi = A y_j; d_j and y_{j+1} = y_j + d_j (0 on held nodes)
+        const uint8_t w = Wc[g];
+        const T rv = rz[g];
+        const T yv = sv[i];
+        const T res = a.dinv[g] * (rv - qi);
+        const T dj = w ? T(0) : T(chc.c1) * (stage == 0 ? yv : a.dv[g]) + T(chc.c2) * res;
+        ydst[g] = w ? T(0) : yv + dj;
+        a.dv[g] = dj;
+        if (stage == 0) {
+          const double sr = double(rv) * double(a.dinv[g]);
+          if (w) {
+            if (w != HELD_FIXED) ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
+          } else {
+            cf = fmax(cf, fabs(sr));
+          }
+        }
+        continue;
+      }
       wn[g] = qi;
+      if (CHEB) {
+        // the A z pass: z = y_cheb, w = A z; the stopping partials came from the main pass
+        const T zv = sv[i];
+        const T rv = rz[g];
+        a.zb[g] = zv;
+        gam += double(rv) * double(zv);
+        del += double(zv) * double(qi);
+        continue;
+      }
       const T zv = sv[i];
       const T rv = rz[g];
       gam += double(rv) * double(zv);
@@ -438,12 +535,22 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       }
     }
   }
+  // with the Chebyshev preconditioner the main pass of a first / iterate
+  // round stores every partial but gamma and delta, the A z pass only those
+  // two, and the Chebyshev steps none
+  uint32_t store = 0xffu;
+  if (CHEB && !xpass) {
+    if (stage > 0 && stage < a.cheb - 1) return;
+    const uint32_t gd = (1u << PT_GAMMA) | (1u << PT_DELTA);
+    store = (stage == 0) ? (0xffu & ~gd) : gd;
+  }
   double v[8] = {del, amin, gam, cf, ca, na, rb, ch};   // in PT_* order
   block_reduce_to0<8, kPartOps>(v, red);
   // partials are stored value-major, [8][n_tiles], so the reduction reads them coalesced
   if (tid == 0) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a.part[size_t(k) * a.dm.n_tiles + tile] = v[k];
+    for (int k = 0; k < 8; ++k)
+      if (store & (1u << k)) a.part[size_t(k) * a.dm.n_tiles + tile] = v[k];
   }
 }
 
@@ -479,6 +586,7 @@ __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* p
   c->iters += 1;
   c->inner = (mode == MODE_ITER) ? c->inner + 1 : 0;
   if (setup && !qp) c->ref = srb;   // linear solves stop relative to max |b_i|/A_ii
+  if (setup) c->lmax = (samin < 0.0) ? -samin : 0.0;   // Gershgorin bound of D^-1 A (Chebyshev only)
   const double tl = tol * c->ref;
   const double rs = c->ref > 0.0 ? c->ref : 1.0;
   if (mode == MODE_RESTART || mode == MODE_CHECK) {
@@ -658,6 +766,9 @@ static DmgArgs<T> dmg_args(pf_mesh_s* m, int kind, const void* H, const void* d_
   a.W1 = m->dw.wset + m->n_nodes;
   a.tol = tol;
   a.max_iter = max_iter;
+  a.zb = a.y0 = a.y1 = a.dv = nullptr;
+  a.cheb = 0;
+  a.stage = 0;
   return a;
 }
 
@@ -675,11 +786,25 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
     timer_end(m, 2, s);
   }
   const int npt = (m->max_own + kBlock - 1) / kBlock;
-  auto kdmg = npt <= 1 ? k_dmg<T, 1> : (npt <= 2 ? k_dmg<T, 2> : (npt <= 4 ? k_dmg<T, 4> : k_dmg<T, 8>));
+  const bool cheb = o->precond >= 2;
+  a.cheb = cheb ? o->precond : 0;
+  a.zb = static_cast<T*>(m->dw.zb);
+  a.y0 = static_cast<T*>(m->dw.y0);
+  a.y1 = static_cast<T*>(m->dw.y1);
+  a.dv = static_cast<T*>(m->dw.dv);
+  auto kdmg = cheb ? (npt <= 1 ? k_dmg<T, 1, true>
+                               : (npt <= 2 ? k_dmg<T, 2, true> : (npt <= 4 ? k_dmg<T, 4, true> : k_dmg<T, 8, true>)))
+                   : (npt <= 1 ? k_dmg<T, 1, false>
+                               : (npt <= 2 ? k_dmg<T, 2, false> : (npt <= 4 ? k_dmg<T, 4, false> : k_dmg<T, 8, false>)));
   auto round = [&]() {
-    timer_begin(m, 1, s);
-    hipLaunchKernelGGL(kdmg, grid, block, lds, s, a);
-    timer_end(m, 1, s);
+    // one pass, or with the Chebyshev preconditioner one pass per matrix-vector product
+    for (int st = 0; st < (cheb ? a.cheb : 1); ++st) {
+      DmgArgs<T> as = a;
+      as.stage = st;
+      timer_begin(m, 1, s);
+      hipLaunchKernelGGL(kdmg, grid, block, lds, s, as);
+      timer_end(m, 1, s);
+    }
     timer_begin(m, 4, s);
     hipLaunchKernelGGL(k_dmg_red, igrid, dim3(kRedBlock), 0, s, m->dw.ctl, m->dw.part, m->n_tiles, m->dw.bounds,
                        kind, o->tol, o->max_iter);
@@ -756,6 +881,7 @@ extern "C" pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const 
   if (d == d_prev) return fail(PF_ERR_ARG, "d must not alias d_prev");
   if (!(opts->tol > 0) || opts->max_iter < 1) return fail(PF_ERR_ARG, "need tol > 0 and max_iter >= 1");
   if (opts->rounds < 0) return fail(PF_ERR_ARG, "rounds must be >= 0");
+  if (opts->precond < 0 || opts->precond > 4) return fail(PF_ERR_ARG, "precond must be in [0, 4]");
   if (opts->resume && !m->qp_started) return fail(PF_ERR_ARG, "resume without a previous damage solve on this handle");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = upload_params(m, p, nullptr, s)) != PF_OK) return st;

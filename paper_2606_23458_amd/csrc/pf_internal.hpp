@@ -69,7 +69,7 @@ struct Ctl {
   int32_t outer;      // active-set updates so far
   double rz, alpha, beta, amax, resid, pq;
   double ref;         // scale of the stopping test (1 for the damage QP, max |b_i|/A_ii for linear solves)
-  double pad2;
+  double lmax;        // upper bound of the spectrum of D^-1 A (set-up pass; Chebyshev preconditioner)
 };
 
 enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2, MODE_CHECK = 3, MODE_FIRST = 4 };
@@ -101,6 +101,9 @@ struct DevWork {
   void* s0; void* s1;                // [n_nodes] A p pair
   void* p;                           // [n_nodes] search direction
   void* xw0; void* xw1;              // [n_nodes] iterate pair of the damage solve
+  void* zb;                          // [n_nodes] z = M r of the current iteration (polynomial preconditioner)
+  void* y0; void* y1;                // [n_nodes] Chebyshev iterate pair (polynomial preconditioner)
+  void* dv;                          // [n_nodes] Chebyshev update direction (polynomial preconditioner)
   uint8_t* wset;                     // [2][n_nodes] held-set pair
   void* lam;                         // [n_nodes] adjoint multiplier (warm start of the next adjoint solve)
   void* hbar;                        // [n_elems] adjoint of H_{n+1} (adjoint step scratch)

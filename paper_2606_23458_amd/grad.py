@@ -112,7 +112,7 @@ class TrajectoryRunner:
         stats = self._stats(n)
         budget = getattr(self, "_fwd_budget", 0) or 32
         o = sim.cg.__class__(sim.cg.tol, sim.cg.max_iter, 0, sim.cg.start, sim.cg.monotone,
-                             min(budget, sim.cg.max_iter), 0)
+                             min(budget, sim.cg.max_iter), 0, sim.cg.precond)
         for j in range(n):
             states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
             sim.explicit(states[j], states[j + 1], sim._loads(self._k0 + j, states[j]))

@@ -202,10 +202,11 @@ class CgConfig:
     monotone: int = 0       # damage solve: 1 = monotone projected CG from the start
     rounds: int = 0         # check_every = 0: CG rounds to enqueue (0 = max_iter)
     resume: int = 0         # damage solve: 1 = continue the handle's previous solve
+    precond: int = 0        # 0: Jacobi; 2-4: Chebyshev-Jacobi polynomial of that degree
 
     def opts(self) -> L.CgOpts:
         return L.CgOpts(self.tol, self.max_iter, self.check_every, self.start, self.monotone, self.rounds,
-                        self.resume)
+                        self.resume, self.precond)
 
 
 def default_tol(dtype: str) -> float:
@@ -440,7 +441,7 @@ class Simulator:
             refs = (self.state, self._next, self.active, self._active_next)
             snap = (self.state.clone(), self._next.d.clone(), self.active.clone())
             o = C.byref(CgConfig(self.cg.tol, self.cg.max_iter, 0, self.cg.start, self.cg.monotone,
-                                 min(budget, self.cg.max_iter), 0).opts())
+                                 min(budget, self.cg.max_iter), 0, self.cg.precond).opts())
             solved = []
             for k in range(w):
                 f = self._loads(self.steps_done + k, self.state)
@@ -529,8 +530,8 @@ class GraphStepper:
         if rounds is None:
             rounds = max(s["iters"] for s in sim.cg_stats()) + 4
         self.rounds, self.more = rounds, more
-        first = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, rounds, 0)
-        cont = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, more, 1)
+        first = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, rounds, 0, base.precond)
+        cont = CgConfig(base.tol, base.max_iter, 0, base.start, base.monotone, more, 1, base.precond)
         self._params = bytes(sim.params)
         self._dt = list(sim.dt)
         self._gc_version = sim.mesh.gc_version
