@@ -247,6 +247,37 @@ def gc_field(steps: int) -> dict:
     return out
 
 
+def preconditioners(steps: int) -> dict:
+    """Jacobi against the Chebyshev-Jacobi polynomials of degree 2-4 on the 1024x512 plate:
+    time per step, CG rounds (one reduction each) and matrix-vector products per solve."""
+    import torch
+    import workloads as w
+    from paper_2606_23458_amd import Simulator
+    from paper_2606_23458_amd.sim import CgConfig, default_tol
+    p = w.config1()
+    out = {}
+    dt = None
+    for deg in (0, 2, 3, 4):
+        sim = Simulator(p, dtype="f32", dt=dt, cg=CgConfig(tol=default_tol("f32"), precond=deg))
+        dt = list(sim.dt)
+        sim.run(20)
+        gpu_sync()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rounds = []
+        ev0.record()
+        for _ in range(steps):
+            sim.step()
+            rounds.append(sim.cg_stats()[0]["iters"])
+        ev1.record()
+        gpu_sync()
+        mean = sum(rounds) / len(rounds)
+        out["jacobi" if deg == 0 else f"chebyshev{deg}"] = {
+            "ms_per_step": round(ev0.elapsed_time(ev1) / steps, 4), "rounds_per_solve": round(mean, 2)}
+    out["note"] = ("polled steps (Simulator.step); a round is one reduction and, with a degree-k "
+                   "polynomial, k passes (restart and check rounds make one)")
+    return out
+
+
 def energies_cost(reps: int = 50) -> dict:
     """pf_energies on the 1024x512 plate: time per call."""
     import torch
@@ -417,7 +448,7 @@ def main():
     if not args.no_extras:
         for key, fn in (("bwd_fwd", bwd_fwd_ratio), ("batched", batched_vs_plain),
                         ("subcycling", lambda: subcycling(100)), ("gc_field", lambda: gc_field(100)),
-                        ("energies", energies_cost)):
+                        ("energies", energies_cost), ("preconditioners", lambda: preconditioners(60))):
             try:
                 out[key] = fn()
             except Exception as e:   # reported on the line; the headline stands on its own
