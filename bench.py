@@ -405,12 +405,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--tile-nodes", type=int, default=0)
+    ap.add_argument("--tile-nodes", default="auto",
+                    help="owned nodes per tile, or 'auto' (the autotuner's choice for this plate)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also copy a 256 MiB device buffer 3 times (known traffic, for counter calibration)")
     args = ap.parse_args()
+    if args.tile_nodes != "auto":
+        args.tile_nodes = int(args.tile_nodes)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -438,6 +441,9 @@ def main():
         "config": {"workload": "1024x512 jittered plate, 1048576 triangles, AT2 / vol-dev / plane strain, "
                                "full staggered step (explicit + projected-CG damage solve)",
                    "n_elems": res["ne"], "n_nodes": res["sim"].mesh.n_nodes, "precision": "fp32 kernels, fp64 CG reductions",
+                   "tile_plan": {"tile_nodes": res["sim"].mesh.tile_nodes, "explicit_block": res["sim"].mesh.explicit_block,
+                                 "explicit_chunks": res["sim"].mesh.explicit_chunks,
+                                 "chosen_by": "autotuner" if args.tile_nodes == "auto" else "command line"},
                    "stepping": "Simulator.run: solver convergence read once per 16 steps, window re-run on a miss"},
         "roofline": roofline(res, 4),
         "explicit_step": explicit_only(res, args.steps),

@@ -92,6 +92,10 @@ typedef struct {
                                 FP32, 256 in FP64) */
     int32_t explicit_block;  /* workgroup size of the explicit-step kernel: 256 or 512;
                                 0 = default (256) */
+    int32_t explicit_chunks; /* element chunks of the explicit step per workgroup:
+                                1, 2, or 0 = automatic (2 when halving the
+                                corner-force space in LDS lets more workgroups
+                                share a CU).  The result does not depend on it. */
 } pf_tile_opts_t;
 
 /* Material and model of one instance (Sec. 2.1-2.2).  Geometry-independent. */
@@ -363,9 +367,12 @@ typedef struct {
     int32_t tile_nodes[PF_TUNE_MAX];
     int32_t status[PF_TUNE_MAX];        /* pf_status_t of each candidate's plan */
     int32_t explicit_block[PF_TUNE_MAX];/* the faster explicit workgroup size (256, 512) */
-    double explicit_us[PF_TUNE_MAX];    /* mean explicit-step time with that workgroup size */
+    double explicit_us[PF_TUNE_MAX];    /* mean explicit-step time with that workgroup size
+                                           and chunk count */
     double cg_round_us[PF_TUNE_MAX];    /* mean damage CG round time */
     double score_us[PF_TUNE_MAX];
+    int32_t best_explicit_chunks;       /* the chosen pf_tile_opts_t.explicit_chunks */
+    int32_t explicit_chunks[PF_TUNE_MAX];/* the faster element chunk count (1, 2) */
 } pf_tune_result_t;
 
 pf_status_t pf_tune_tiles(const pf_mesh_desc_t* inst, int32_t n_instances, pf_dtype_t dtype,

@@ -28,7 +28,7 @@ class MeshDesc(C.Structure):
 
 
 class TileOpts(C.Structure):
-    _fields_ = [("tile_nodes", C.c_int32), ("explicit_block", C.c_int32)]
+    _fields_ = [("tile_nodes", C.c_int32), ("explicit_block", C.c_int32), ("explicit_chunks", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -75,7 +75,8 @@ class TuneResult(C.Structure):
     _fields_ = [("best", C.c_int32), ("best_explicit_block", C.c_int32), ("n_tried", C.c_int32),
                 ("tile_nodes", C.c_int32 * PF_TUNE_MAX), ("status", C.c_int32 * PF_TUNE_MAX),
                 ("explicit_block", C.c_int32 * PF_TUNE_MAX), ("explicit_us", C.c_double * PF_TUNE_MAX),
-                ("cg_round_us", C.c_double * PF_TUNE_MAX), ("score_us", C.c_double * PF_TUNE_MAX)]
+                ("cg_round_us", C.c_double * PF_TUNE_MAX), ("score_us", C.c_double * PF_TUNE_MAX),
+                ("best_explicit_chunks", C.c_int32), ("explicit_chunks", C.c_int32 * PF_TUNE_MAX)]
 
 
 class PfError(RuntimeError):

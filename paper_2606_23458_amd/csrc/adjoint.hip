@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
     qc[3 * e + 0] = kA * (g0x * glx + g0y * gly) + mA * (l0v + ls);
     qc[3 * e + 1] = kA * (g1x * glx + g1y * gly) + mA * (l1v + ls);
     qc[3 * e + 2] = kA * (g2x * glx + g2y * gly) + mA * (l2v + ls);
-    if (e < t.n_own_elem) {
+    if (e >= t.own_elem_lo && e < t.own_elem_lo + t.n_own_elem) {
       const T d0 = sd[c0], d1 = sd[c1], d2 = sd[c2];
       const T gdx = g0x * d0 + g1x * d1 + g2x * d2;
       const T gdy = g0y * d0 + g1y * d1 + g2y * d2;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
     cdd[3 * e + 0] = db;
     cdd[3 * e + 1] = db;
     cdd[3 * e + 2] = db;
-    if (e < t.n_own_elem) adj0.H[gid] = won ? T(0) : hb;
+    if (e >= t.own_elem_lo && e < t.own_elem_lo + t.n_own_elem) adj0.H[gid] = won ? T(0) : hb;
   }
   __syncthreads();
   for (int i = tid; i < t.n_own; i += kBlock) {

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(DevMesh dm, const InstP<T>* _
   const bool at2 = P.model == PF_AT2;
   const T* __restrict__ gcs = static_cast<const T*>(dm.gcs);
   for (int e = tid; e < t.n_own_elem; e += kBlock) {
-    const int te = t.telem_begin + e;
+    const int te = t.telem_begin + t.own_elem_lo + e;
     const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
     const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
     const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];

@@ -7,7 +7,11 @@
 // Phase 2 evaluates every element touching an owned node and stores its three
 // corner forces in LDS; owned elements also update H.  Phase 3 sums, for each
 // owned node, its corner forces in ascending element order (no atomics, so
-// the result is bitwise reproducible) and applies the corrector.
+// the result is bitwise reproducible) and applies the corrector.  Phases 2
+// and 3 may run over the tile's elements in two chunks, which halves the
+// corner-force space in LDS so that more workgroups fit on a CU; a node's
+// corner list is sorted by element, so each chunk adds a contiguous run of
+// it and the sums keep their order.
 #include "device_common.hpp"
 #include "split.hpp"
 
@@ -15,17 +19,18 @@ namespace pf {
 
 template <typename T, int S, int NPT, int BS>
 __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> in,
-                                                 StateOut<T> out, const T* __restrict__ fext) {
+                                                 StateOut<T> out, const T* __restrict__ fext, int nch) {
   const TileRec t = dm.tiles[tile_of_block(dm.n_tiles)];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
+  const int chs = (t.n_telem + nch - 1) / nch;   // elements per chunk
   T* sux = reinterpret_cast<T*>(smem);
   T* suy = sux + nloc;
   T* sd = suy + nloc;
   T* sfx = sd + nloc;
-  T* sfy = sfx + 3 * t.n_telem;
-  uint16_t* coffs = reinterpret_cast<uint16_t*>(sfy + 3 * t.n_telem);   // [n_own + 1] corner-list offsets
+  T* sfy = sfx + 3 * chs;
+  uint16_t* coffs = reinterpret_cast<uint16_t*>(sfy + 3 * chs);         // [n_own + 1] corner-list offsets
   uint16_t* clist = coffs + t.n_own + 1;                                // [n_corner] corner ids
   const int tid = threadIdx.x;
   stage_corners(dm, t, coffs, clist);
@@ -56,10 +61,22 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   }
   __syncthreads();
 
-  // ---- phase 2: element strain, split, stress, corner forces, history ------
+  // ---- phases 2 and 3a, per chunk of elements ------------------------------
   const T* __restrict__ geo = static_cast<const T*>(dm.geo);
   const size_t nte = size_t(dm.n_te);
-  for (int e = tid; e < t.n_telem; e += BS) {
+  T fxa[NPT], fya[NPT];
+  int jc[NPT];   // next corner of each owned node
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * BS;
+    fxa[r] = T(0), fya[r] = T(0);
+    jc[r] = (i < t.n_own) ? coffs[i] : 0;
+  }
+  for (int e0 = 0; e0 < t.n_telem; e0 += chs) {
+  const int e1 = min(e0 + chs, t.n_telem);
+  if (e0 > 0) __syncthreads();   // the previous chunk's corner forces have been added
+  // phase 2: element strain, split, stress, corner forces, history
+  for (int e = e0 + tid; e < e1; e += BS) {
     const int te = t.telem_begin + e;
     const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
     const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
@@ -73,21 +90,42 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
     const T om = T(1) - de;
     const T gd = om * om + P.eta;
     const T sxx = gd * sp[0] + sm[0], syy = gd * sp[1] + sm[1], sxy = gd * sp[2] + sm[2];
-    sfx[3 * e + 0] = A * (sxx * g0x + sxy * g0y);
-    sfy[3 * e + 0] = A * (sxy * g0x + syy * g0y);
-    sfx[3 * e + 1] = A * (sxx * g1x + sxy * g1y);
-    sfy[3 * e + 1] = A * (sxy * g1x + syy * g1y);
-    sfx[3 * e + 2] = A * (sxx * g2x + sxy * g2y);
-    sfy[3 * e + 2] = A * (sxy * g2x + syy * g2y);
-    if (e < t.n_own_elem) {
-      const int gid = t.own_elem_begin + e;
+    const int l = e - e0;
+    sfx[3 * l + 0] = A * (sxx * g0x + sxy * g0y);
+    sfy[3 * l + 0] = A * (sxy * g0x + syy * g0y);
+    sfx[3 * l + 1] = A * (sxx * g1x + sxy * g1y);
+    sfy[3 * l + 1] = A * (sxy * g1x + syy * g1y);
+    sfx[3 * l + 2] = A * (sxx * g2x + sxy * g2y);
+    sfy[3 * l + 2] = A * (sxy * g2x + syy * g2y);
+    if (e >= t.own_elem_lo && e < t.own_elem_lo + t.n_own_elem) {
+      const int gid = t.own_elem_begin + (e - t.own_elem_lo);
       const T Hn = in.H[gid];
       out.H[gid] = psi_p > Hn ? psi_p : Hn;
     }
   }
   __syncthreads();
+  // phase 3a: each owned node adds the corners of this chunk, in list order
+  const int cend = 3 * e1, cbeg = 3 * e0;
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * BS;
+    if (i < t.n_own) {
+      const int j1 = coffs[i + 1];
+      int j = jc[r];
+      T fx = fxa[r], fy = fya[r];
+      for (; j < j1; ++j) {
+        const int c = clist[j];
+        if (c >= cend) break;
+        fx += sfx[c - cbeg];
+        fy += sfy[c - cbeg];
+      }
+      jc[r] = j;
+      fxa[r] = fx, fya[r] = fy;
+    }
+  }
+  }
 
-  // ---- phase 3: gather f_int, corrector (eq. vv_a, eq. vv_v) ---------------
+  // ---- phase 3b: corrector (eq. vv_a, eq. vv_v) ----------------------------
   const T* __restrict__ invw = static_cast<const T*>(dm.inv_w);
   const size_t N = size_t(dm.n_nodes);
 #pragma unroll
@@ -95,13 +133,7 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
     const int i = tid + r * BS;
     if (i < t.n_own) {
       const int g = t.node_begin + i;
-      const int j0 = coffs[i], j1 = coffs[i + 1];
-      T fx = T(0), fy = T(0);
-      for (int j = j0; j < j1; ++j) {
-        const int c = clist[j];
-        fx += sfx[c];
-        fy += sfy[c];
-      }
+      const T fx = fxa[r], fy = fya[r];
       const T minv = P.inv_rho * invw[g];
       const uint8_t fl = dm.fixed[g];
       const T ex = fext ? fext[g] : T(0);
@@ -116,10 +148,21 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   }
 }
 
+// Two element chunks when that lets more workgroups share a CU (LDS-bound
+// occupancy); the workgroups per CU are capped by the CU's thread slots.
+static int explicit_chunks(const pf_mesh_s* m, int bs) {
+  if (m->explicit_chunks > 0) return m->explicit_chunks;
+  const int cap = std::max(1, m->threads_per_cu / bs);
+  const int occ1 = std::min(cap, m->lds_per_cu / std::max(1, m->max_lds_explicit));
+  const int occ2 = std::min(cap, m->lds_per_cu / std::max(1, m->max_lds_explicit2));
+  return occ2 > occ1 ? 2 : 1;
+}
+
 template <typename T, int S>
 static hipError_t launch_explicit_s(pf_mesh_s* m, const pf_state_t* in, pf_state_t* out, const void* fext,
                                     hipStream_t s) {
-  const size_t lds = m->max_lds_explicit;
+  const int nch = explicit_chunks(m, m->explicit_block);
+  const size_t lds = nch == 2 ? m->max_lds_explicit2 : m->max_lds_explicit;
   const InstP<T>* ip = static_cast<const InstP<T>*>(m->dw.instp);
   auto si = state_in<T>(in);
   auto so = state_out<T>(out);
@@ -128,22 +171,22 @@ static hipError_t launch_explicit_s(pf_mesh_s* m, const pf_state_t* in, pf_state
   if (m->explicit_block == 512) {
     const int npt = (m->max_own + 511) / 512;
     if (npt <= 1)
-      hipLaunchKernelGGL((k_explicit<T, S, 1, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 1, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch);
     else if (npt <= 2)
-      hipLaunchKernelGGL((k_explicit<T, S, 2, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 2, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch);
     else
-      hipLaunchKernelGGL((k_explicit<T, S, 4, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 4, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch);
   } else {
     const int npt = (m->max_own + kBlock - 1) / kBlock;
     const dim3 block(kBlock);
     if (npt <= 1)
-      hipLaunchKernelGGL((k_explicit<T, S, 1, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 1, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
     else if (npt <= 2)
-      hipLaunchKernelGGL((k_explicit<T, S, 2, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 2, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
     else if (npt <= 4)
-      hipLaunchKernelGGL((k_explicit<T, S, 4, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 4, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
     else
-      hipLaunchKernelGGL((k_explicit<T, S, 8, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe);
+      hipLaunchKernelGGL((k_explicit<T, S, 8, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
   }
   return hipGetLastError();
 }

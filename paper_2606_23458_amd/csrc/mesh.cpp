@@ -1,6 +1,7 @@
 // Mesh handle: validation, P1 geometry (eq. grad_phi, lumped mass), tile plan,
 // device upload, per-instance parameters, error reporting and kernel timers.
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -248,6 +249,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   if (tile_nodes < 64 || tile_nodes > kMaxTileNodes) return fail(PF_ERR_ARG, "tile_nodes must be in [64, 2048]");
   const int explicit_block = (tile && tile->explicit_block > 0) ? tile->explicit_block : kBlock;
   if (explicit_block != 256 && explicit_block != 512) return fail(PF_ERR_ARG, "explicit_block must be 256 or 512");
+  const int explicit_chunks = tile ? tile->explicit_chunks : 0;
+  if (explicit_chunks < 0 || explicit_chunks > 2) return fail(PF_ERR_ARG, "explicit_chunks must be 0, 1 or 2");
 
   // ---- validate and count -------------------------------------------------
   int64_t n_tot = 0, e_tot = 0;
@@ -265,6 +268,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   if (!m) return fail(PF_ERR_NOMEM, "host allocation failed");
   m->dtype = dtype;
   m->explicit_block = explicit_block;
+  m->explicit_chunks = explicit_chunks;
   m->n_inst = n_instances;
   m->n_nodes = int32_t(n_tot);
   m->n_elems = int32_t(e_tot);
@@ -406,8 +410,14 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
           return fail(PF_ERR_MESH, "internal: owned elements are not contiguous");
         }
       own_elem_cursor += rec.n_own_elem;
-      std::vector<int32_t> tel(owned_e);
-      tel.insert(tel.end(), halo_e.begin(), halo_e.end());
+      // tile elements in ascending internal id: halo elements of earlier
+      // tiles, the owned run, then halo elements of later tiles
+      std::vector<int32_t> tel;
+      tel.reserve(owned_e.size() + halo_e.size());
+      std::merge(owned_e.begin(), owned_e.end(), halo_e.begin(), halo_e.end(), std::back_inserter(tel), by_int);
+      rec.own_elem_lo =
+          owned_e.empty() ? 0
+                          : int32_t(std::lower_bound(tel.begin(), tel.end(), owned_e.front(), by_int) - tel.begin());
       rec.n_telem = int32_t(tel.size());
       rec.telem_begin = int32_t(te_gid.size());
       // local node numbering: owned first, then halo by internal id
@@ -444,14 +454,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
         std::vector<std::pair<int32_t, int32_t>> cs;   // (internal elem id, corner id)
         for (int32_t j = adj_ptr[u]; j < adj_ptr[u + 1]; ++j) {
           int32_t e = adj[j];
-          auto it = std::lower_bound(tel.begin(), tel.begin() + rec.n_own_elem, e, by_int);
-          int32_t pos;
-          if (it != tel.begin() + rec.n_own_elem && *it == e) {
-            pos = int32_t(it - tel.begin());
-          } else {
-            auto it2 = std::lower_bound(tel.begin() + rec.n_own_elem, tel.end(), e, by_int);
-            pos = int32_t(it2 - tel.begin());
-          }
+          const int32_t pos = int32_t(std::lower_bound(tel.begin(), tel.end(), e, by_int) - tel.begin());
           int q = (tri[3 * e] == u) ? 0 : (tri[3 * e + 1] == u ? 1 : 2);
           cs.emplace_back(elem_int[e], 3 * pos + q);
         }
@@ -498,7 +501,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
       if (t.n_own < 1 || t.n_own > kMaxTileNodes) bad = "owned node count out of range";
       if (t.halo_begin < 0 || int64_t(t.halo_begin) + t.n_halo > int64_t(halo_idx.size())) bad = "halo range";
       if (t.telem_begin < 0 || int64_t(t.telem_begin) + t.n_telem > int64_t(m->n_te)) bad = "element range";
-      if (t.n_own_elem > t.n_telem || t.own_elem_begin < 0 || t.own_elem_begin + t.n_own_elem > m->n_elems)
+      if (t.n_own_elem > t.n_telem || t.own_elem_begin < 0 || t.own_elem_begin + t.n_own_elem > m->n_elems ||
+          t.own_elem_lo < 0 || t.own_elem_lo + t.n_own_elem > t.n_telem)
         bad = "owned element range";
       for (int32_t j = 0; j < t.n_halo && bad.empty(); ++j) {
         int32_t g = halo_idx[t.halo_begin + j];
@@ -508,13 +512,15 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
         const int32_t te = t.telem_begin + e;
         if (lc[0][te] >= nloc || lc[1][te] >= nloc || lc[2][te] >= nloc) bad = "local connectivity";
         if (te_gid[te] < 0 || te_gid[te] >= m->n_elems) bad = "element id";
-        if (e < t.n_own_elem && te_gid[te] != t.own_elem_begin + e) bad = "owned element id";
+        if (e >= t.own_elem_lo && e < t.own_elem_lo + t.n_own_elem && te_gid[te] != t.own_elem_begin + e - t.own_elem_lo)
+          bad = "owned element id";
+        if (e > 0 && te_gid[te] <= te_gid[te - 1]) bad = "element order";
       }
       for (int32_t i = 0; i < t.n_own && bad.empty(); ++i) {
         const int32_t g = t.node_begin + i;
         if (lrow[g + 1] < lrow[g] || lrow[g + 1] - lrow[g] < 1) bad = "corner list";
         for (int32_t j = lrow[g]; j < lrow[g + 1] && bad.empty(); ++j)
-          if (lcorner[j] >= 3 * t.n_telem) bad = "corner id";
+          if (lcorner[j] >= 3 * t.n_telem || (j > lrow[g] && lcorner[j] <= lcorner[j - 1])) bad = "corner id";
       }
       // the kernels stage the corner lists in LDS with 16-bit offsets
       if (bad.empty() && (t.n_corner < t.n_own || t.n_corner > 65535 || t.corner_begin != lrow[t.node_begin] ||
@@ -625,11 +631,19 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   // plus, in both, the owned nodes' corner lists (16-bit offsets and ids)
   const size_t lists = 2 * (size_t(m->max_own) + 1 + size_t(m->max_corner));
   m->max_lds_explicit = int32_t((3 * size_t(max_loc) + 6 * size_t(max_te)) * w + lists + 64);
+  m->max_lds_explicit2 = int32_t((3 * size_t(max_loc) + 6 * ((size_t(max_te) + 1) / 2)) * w + lists + 64);
   m->max_lds_damage = int32_t(((size_t(max_loc) * w + lists + 7) & ~size_t(7)) + size_t(max_te) * 3 * w + 64);
   int dev = 0, lds_limit = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_limit <= 0)
     lds_limit = 65536;
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
+      m->lds_per_cu = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) == hipSuccess && v > 0)
+      m->threads_per_cu = v;
+  }
   if (std::max(m->max_lds_explicit, m->max_lds_damage) > lds_limit) {
     std::string s = "tiles need " + std::to_string(std::max(m->max_lds_explicit, m->max_lds_damage)) +
                     " bytes of LDS, device allows " + std::to_string(lds_limit) + "; lower tile_nodes";

@@ -16,8 +16,10 @@ constexpr int kMaxTileNodes = 2048;  // owned nodes per tile, upper limit
 constexpr int kWaves = kBlock / 64;
 
 // One tile: a contiguous range of owned nodes plus the halo needed to
-// evaluate every element that touches them.  Owned elements come first in
-// the tile's element list and carry consecutive internal element ids.
+// evaluate every element that touches them.  The tile's element list is in
+// ascending internal element id; the owned elements carry consecutive ids, so
+// they form one run of it, and every owned node's corner list (ascending
+// element id) is ascending in the local element index too.
 struct TileRec {
   int32_t node_begin;      // first owned node (internal id)
   int32_t n_own;           // owned nodes
@@ -25,12 +27,13 @@ struct TileRec {
   int32_t n_halo;          // halo nodes (local ids n_own .. n_own+n_halo-1)
   int32_t telem_begin;     // offset into the tile-element arrays
   int32_t n_telem;         // elements evaluated by this tile (owned + halo)
-  int32_t n_own_elem;      // owned elements (first n_own_elem of the list)
+  int32_t n_own_elem;      // owned elements, local indices own_elem_lo .. own_elem_lo + n_own_elem - 1
   int32_t own_elem_begin;  // internal id of the first owned element
   int32_t inst;            // instance
   int32_t lds_bytes;       // dynamic LDS this tile needs (explicit kernel, FP64 upper bound)
   int32_t corner_begin;    // first entry of the owned nodes' corner lists (lcorner index)
   int32_t n_corner;        // entries in the owned nodes' corner lists
+  int32_t own_elem_lo;     // local index of the first owned element
 };
 
 // Per-instance constants for the kernels, in the arithmetic type T.
@@ -129,6 +132,10 @@ struct pf_mesh_s {
   int32_t max_tile_nodes = 0, max_tile_elems = 0, max_own = 0, max_lds_explicit = 0, max_lds_damage = 0;
   int32_t max_corner = 0;
   int32_t explicit_block = 256;      // workgroup size of the explicit-step kernel (256 or 512)
+  int32_t max_lds_explicit2 = 0;     // LDS of the explicit step with its elements in two chunks
+  int32_t explicit_chunks = 0;       // 1, 2, or 0 = automatic
+  int32_t lds_per_cu = 160 * 1024;   // device limits that set how many workgroups share a CU
+  int32_t threads_per_cu = 2048;
   int32_t split = -1;
   std::vector<pf_instance_info_t> info;
   std::vector<int32_t> node_perm, elem_perm;

@@ -37,9 +37,9 @@ constexpr int kDefaultCandidates[] = {128, 192, 256, 384, 512, 768, 1024};
 // Time `reps` explicit steps and `reps` damage CG rounds of one tile plan.
 pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dtype, const pf_params_t* p,
                       int32_t tile_nodes, int32_t reps, hipStream_t s, double* explicit_us, int32_t* explicit_block,
-                      double* round_us) {
+                      int32_t* explicit_chunks, double* round_us) {
   Handle h;
-  pf_tile_opts_t to{tile_nodes, 0};
+  pf_tile_opts_t to{tile_nodes, 0, 0};
   pf_status_t st = pf_mesh_create(inst, n_inst, dtype, &to, s, &h.m);
   if (st != PF_OK) return st;
   pf_mesh_s* m = h.m;
@@ -62,11 +62,13 @@ pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dty
   Events ev;
   PF_HIP(hipEventCreate(&ev.a));
   PF_HIP(hipEventCreate(&ev.b));
-  // explicit step, with each workgroup size
+  // explicit step, with each workgroup size and element chunk count
   float ms = 0.f;
   *explicit_us = 0.0;
-  for (int bs : {256, 512}) {
+  for (int cfg = 0; cfg < 4; ++cfg) {
+    const int bs = (cfg & 1) ? 512 : 256, nch = (cfg & 2) ? 2 : 1;
     m->explicit_block = bs;
+    m->explicit_chunks = nch;
     for (int k = 0; k < 2; ++k)
       if ((st = pf_explicit_step(m, p, dt.data(), &st2[k & 1], &st2[(k + 1) & 1], nullptr, s)) != PF_OK) return st;
     PF_HIP(hipEventRecord(ev.a, s));
@@ -79,6 +81,7 @@ pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dty
     if (*explicit_us == 0.0 || us < *explicit_us) {
       *explicit_us = us;
       *explicit_block = bs;
+      *explicit_chunks = nch;
     }
   }
   // damage CG rounds: a linear solve on all nodes with a positive right-hand
@@ -138,20 +141,22 @@ extern "C" pf_status_t pf_tune_tiles(const pf_mesh_desc_t* inst, int32_t n_insta
   for (size_t k = 0; k < cand.size(); ++k) {
     out->tile_nodes[k] = cand[k];
     double te = 0.0, tr = 0.0;
-    int32_t eb = 256;
-    const pf_status_t st = time_plan(inst, n_instances, dtype, p, cand[k], reps, s, &te, &eb, &tr);
+    int32_t eb = 256, ec = 1;
+    const pf_status_t st = time_plan(inst, n_instances, dtype, p, cand[k], reps, s, &te, &eb, &ec, &tr);
     out->status[k] = st;
     out->n_tried = int32_t(k + 1);
     if (st == PF_ERR_UNSUPPORTED) continue;   // the plan needs more LDS than a workgroup has
     if (st != PF_OK) return st;               // a real error: pf_last_error() holds its text
     out->explicit_us[k] = te;
     out->explicit_block[k] = eb;
+    out->explicit_chunks[k] = ec;
     out->cg_round_us[k] = tr;
     out->score_us[k] = te + weight * tr;
     if (out->best == 0 || out->score_us[k] < best) {
       best = out->score_us[k];
       out->best = cand[k];
       out->best_explicit_block = eb;
+      out->best_explicit_chunks = ec;
     }
   }
   if (out->best == 0) return fail(PF_ERR_UNSUPPORTED, "no candidate tile size fits the device's LDS");

@@ -37,12 +37,15 @@ class Mesh:
     """
 
     def __init__(self, meshes, dtype: str = "f64", tile_nodes: int = 0, device: str = "cuda",
-                 explicit_block: int = 0):
+                 explicit_block: int = 0, explicit_chunks: int = 0):
         if dtype not in ("f32", "f64"):
             raise ValueError(dtype)
         self.dtype_code = dtype
         self.dtype = torch_dtype(dtype)
         self.device = torch.device(device)
+        # as requested (0: default)
+        self.tile_nodes, self.explicit_block, self.explicit_chunks = int(tile_nodes), int(explicit_block), \
+            int(explicit_chunks)
         n = len(meshes)
         keep = []
         descs = (L.MeshDesc * n)()
@@ -54,7 +57,7 @@ class Mesh:
             descs[k] = L.MeshDesc(len(xy), len(tri), xy.ctypes.data, tri.ctypes.data,
                                   None if fx is None else fx.ctypes.data)
         h = C.c_void_p()
-        opts = L.TileOpts(int(tile_nodes), int(explicit_block))
+        opts = L.TileOpts(int(tile_nodes), int(explicit_block), int(explicit_chunks))
         L.call("pf_mesh_create", descs, n, L.PF_F64 if dtype == "f64" else L.PF_F32, C.byref(opts),
                _stream(), C.byref(h))
         self.handle = h
@@ -292,12 +295,13 @@ class Simulator:
             problems = [problems]
         self.problems = list(problems)
         self.dtype_code = dtype or self.problems[0].dtype
-        explicit_block = 0
+        explicit_block = explicit_chunks = 0
         if mesh is None and tile_nodes == "auto":
             from .tune import tune_tiles
             rep = tune_tiles(self.problems, self.dtype_code)
-            tile_nodes, explicit_block = rep["best"], rep["explicit_block"]
-        self.mesh = mesh or Mesh(self.problems, self.dtype_code, tile_nodes, explicit_block=explicit_block)
+            tile_nodes, explicit_block, explicit_chunks = rep["best"], rep["explicit_block"], rep["explicit_chunks"]
+        self.mesh = mesh or Mesh(self.problems, self.dtype_code, tile_nodes, explicit_block=explicit_block,
+                                 explicit_chunks=explicit_chunks)
         n = len(self.problems)
         self.params = (L.Params * n)(*[params_of(p) for p in self.problems])
         self.dt = (C.c_double * n)()

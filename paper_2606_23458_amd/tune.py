@@ -57,9 +57,11 @@ def tune_tiles(problems, dtype: str, candidates=None, reps: int = 20, cg_rounds_
     rows = []
     for k in range(res.n_tried):
         rows.append({"tile_nodes": res.tile_nodes[k], "status": L.STATUS_NAMES.get(res.status[k], res.status[k]),
-                     "explicit_block": res.explicit_block[k], "explicit_us": round(res.explicit_us[k], 3),
+                     "explicit_block": res.explicit_block[k], "explicit_chunks": res.explicit_chunks[k],
+                     "explicit_us": round(res.explicit_us[k], 3),
                      "cg_round_us": round(res.cg_round_us[k], 3), "score_us": round(res.score_us[k], 3)})
-    out = {"best": int(res.best), "explicit_block": int(res.best_explicit_block), "size_class": key,
+    out = {"best": int(res.best), "explicit_block": int(res.best_explicit_block),
+           "explicit_chunks": int(res.best_explicit_chunks), "size_class": key,
            "candidates": rows}
     if use_cache and candidates is None:
         _CACHE[key] = out

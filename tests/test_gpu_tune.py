@@ -54,3 +54,17 @@ def test_explicit_workgroup_sizes_agree_bitwise():
     b.step(6)
     torch.cuda.synchronize()
     assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
+
+
+@pytest.mark.parametrize("block", [256, 512])
+def test_explicit_element_chunks_agree_bitwise(block):
+    """One or two element chunks per workgroup add each node's corner forces in the same order."""
+    from paper_2606_23458_amd import Mesh, Simulator
+    p = w.small_plate(48, 24, seed=2)
+    a = Simulator(p, dtype="f32", mesh=Mesh([p], "f32", 256, explicit_block=block, explicit_chunks=1))
+    b = Simulator(p, dtype="f32", mesh=Mesh([p], "f32", 256, explicit_block=block, explicit_chunks=2),
+                  dt=list(a.dt))
+    a.step(8)
+    b.step(8)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
