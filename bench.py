@@ -34,17 +34,19 @@ HBM_PEAK_GBS = 8000.0
 #   pointer), elements 24 + 9w (connectivity, 6 grad phi + area, H read and
 #   written, 3 corner ids); with N ~ N_e/2 that is 90 B (w = 4), 154 B (w = 8).
 #   damage CG iteration pass: nodes 11w + 1 (r, A z, A p, p, x, D^-1 and the
-#   held flag read; p, A p, x, r, A z written), elements 8w + 24 (grad phi,
-#   area, per-solve mass coefficient, connectivity, corner ids): 78.5 B (w = 4).
-#   The restart and check passes move fewer bytes; the family is costed at the
-#   iteration pass, which is most of its launches.
+#   held flag read; p, A p, x, r, A z written), elements 4w + 24 (the three
+#   off-diagonal entries of the element stiffness, which the pass reads in
+#   place of the gradients and the area, the per-solve mass coefficient,
+#   connectivity, corner ids): 62.5 B (w = 4).  The restart and check passes
+#   move fewer bytes; the family is costed at the iteration pass, which is
+#   most of its launches.
 
 
 def alg_bytes_per_elem(family: int, w: int) -> float:
     if family == 0:
         return (14 * w + 4) / 2 + 24 + 9 * w
     if family == 1:
-        return (11 * w + 1) / 2 + 8 * w + 24
+        return (11 * w + 1) / 2 + 4 * w + 24
     raise ValueError(family)
 
 

@@ -301,6 +301,11 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   // per-element toughness factor phi_e (Gc_e = Gc phi_e) scales every Gc
   // term of the element's operator and load; absent, phi_e = 1 exactly
   const T* __restrict__ gcs = static_cast<const T*>(a.dm.gcs);
+  // the element operator is kap phi_e K^e + mA (1 + delta_kl) with K^e given by
+  // its off-diagonals K01, K02, K12 (rows of K^e sum to zero), so a pass reads
+  // three values per element instead of the six gradients and the area:
+  //   (A^e z)_k = kap phi_e sum_{l != k} K_kl (z_l - z_k) + mA (z_k + z_0 + z_1 + z_2)
+  const T* __restrict__ kw = static_cast<const T*>(a.dm.kw);
   if (setup) {
     T dacc[NPT], bacc[NPT], sacc[NPT];
 #pragma unroll
@@ -318,23 +323,24 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       __syncthreads();
       for (int e = e0 + tid; e < e1; e += kBlock) {
         const int te = t.telem_begin + e;
-        const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-        const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+        const T A = geo[6 * nte + te];
+        const T w01 = kw[te], w02 = kw[nte + te], w12 = kw[2 * nte + te];
         const T ph = gcs ? gcs[te] : T(1);
-        const T kA = P.kap * ph * A;
+        const T kp = P.kap * ph;
         const T He = a.H[a.dm.te_gid[te]];
         const T mA = (P.c0 * ph + P.cH * He) * A * T(1.0 / 12.0);
         a.mte[te] = mA;
         const int l = e - e0;
-        dc[3 * l + 0] = kA * (g0x * g0x + g0y * g0y) + T(2) * mA;
-        dc[3 * l + 1] = kA * (g1x * g1x + g1y * g1y) + T(2) * mA;
-        dc[3 * l + 2] = kA * (g2x * g2x + g2y * g2y) + T(2) * mA;
+        // diagonal of K^e from the zero row sums
+        dc[3 * l + 0] = kp * -(w01 + w02) + T(2) * mA;
+        dc[3 * l + 1] = kp * -(w01 + w12) + T(2) * mA;
+        dc[3 * l + 2] = kp * -(w02 + w12) + T(2) * mA;
         bc[3 * chs + l] = qp ? (P.b0 * ph + P.bH * He) * A * T(1.0 / 3.0) : T(0);
         if (CHEB) {
-          // off-diagonal entries kA grad phi_k . grad phi_l + mA of the element matrix
-          const T o01 = fabs(kA * (g0x * g1x + g0y * g1y) + mA);
-          const T o02 = fabs(kA * (g0x * g2x + g0y * g2y) + mA);
-          const T o12 = fabs(kA * (g1x * g2x + g1y * g2y) + mA);
+          // off-diagonal entries of the element matrix
+          const T o01 = fabs(kp * w01 + mA);
+          const T o02 = fabs(kp * w02 + mA);
+          const T o12 = fabs(kp * w12 + mA);
           sc_[3 * l + 0] = dc[3 * l + 0] + o01 + o02;
           sc_[3 * l + 1] = dc[3 * l + 1] + o01 + o12;
           sc_[3 * l + 2] = dc[3 * l + 2] + o02 + o12;
@@ -389,19 +395,14 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       for (int e = e0 + tid; e < e1; e += kBlock) {
         const int te = t.telem_begin + e;
         const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
-        const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-        const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-        const T kA = P.kap * (gcs ? gcs[te] : T(1)) * A;
-        const T mA = a.mte[te];
+        const double w01 = kw[te], w02 = kw[nte + te], w12 = kw[2 * nte + te];
+        const double k = double(P.kap * (gcs ? gcs[te] : T(1))), mm = double(a.mte[te]);
         const double s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
-        const double gpx = double(g0x) * s0 + double(g1x) * s1 + double(g2x) * s2;
-        const double gpy = double(g0y) * s0 + double(g1y) * s1 + double(g2y) * s2;
         const double ss = s0 + s1 + s2;
-        const double k = kA, mm = mA;
         const int l = e - e0;
-        qd[3 * l + 0] = k * (double(g0x) * gpx + double(g0y) * gpy) + mm * (s0 + ss);
-        qd[3 * l + 1] = k * (double(g1x) * gpx + double(g1y) * gpy) + mm * (s1 + ss);
-        qd[3 * l + 2] = k * (double(g2x) * gpx + double(g2y) * gpy) + mm * (s2 + ss);
+        qd[3 * l + 0] = k * (w01 * (s1 - s0) + w02 * (s2 - s0)) + mm * (s0 + ss);
+        qd[3 * l + 1] = k * (w01 * (s0 - s1) + w12 * (s2 - s1)) + mm * (s1 + ss);
+        qd[3 * l + 2] = k * (w02 * (s0 - s2) + w12 * (s1 - s2)) + mm * (s2 + ss);
       }
       __syncthreads();
 #pragma unroll
@@ -472,17 +473,14 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     for (int e = tid; e < t.n_telem; e += kBlock) {
       const int te = t.telem_begin + e;
       const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
-      const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-      const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-      const T kA = P.kap * (gcs ? gcs[te] : T(1)) * A;
+      const T w01 = kw[te], w02 = kw[nte + te], w12 = kw[2 * nte + te];
+      const T kp = P.kap * (gcs ? gcs[te] : T(1));
       const T mA = a.mte[te];
       const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
-      const T gpx = g0x * s0 + g1x * s1 + g2x * s2;
-      const T gpy = g0y * s0 + g1y * s1 + g2y * s2;
       const T ss = s0 + s1 + s2;
-      qc[3 * e + 0] = kA * (g0x * gpx + g0y * gpy) + mA * (s0 + ss);
-      qc[3 * e + 1] = kA * (g1x * gpx + g1y * gpy) + mA * (s1 + ss);
-      qc[3 * e + 2] = kA * (g2x * gpx + g2y * gpy) + mA * (s2 + ss);
+      qc[3 * e + 0] = kp * (w01 * (s1 - s0) + w02 * (s2 - s0)) + mA * (s0 + ss);
+      qc[3 * e + 1] = kp * (w01 * (s0 - s1) + w12 * (s2 - s1)) + mA * (s1 + ss);
+      qc[3 * e + 2] = kp * (w02 * (s0 - s2) + w12 * (s1 - s2)) + mA * (s2 + ss);
     }
     __syncthreads();
     T* wn = iter ? wn_ : (cur1 ? a.w1 : a.w0);

@@ -50,10 +50,29 @@ __device__ __forceinline__ int tile_of_block(int n_tiles) {
 // index node i's entries of cl, which are tile-local corner ids 3 e + k in
 // ascending element id.  Coalesced loads by the whole block; the caller
 // synchronises before reading.
+// Each thread issues the loads of kStageBatch entries before it stores any of
+// them, so a tile's lists arrive in a few memory round trips rather than one
+// per block-wide stride (indices past the end are clamped to the last entry).
+constexpr int kStageBatch = 8;
 __device__ __forceinline__ void stage_corners(const DevMesh& dm, const TileRec& t, uint16_t* offs, uint16_t* cl) {
-  for (int i = threadIdx.x; i <= t.n_own; i += blockDim.x)
-    offs[i] = uint16_t(dm.lrow[t.node_begin + i] - t.corner_begin);
-  for (int k = threadIdx.x; k < t.n_corner; k += blockDim.x) cl[k] = dm.lcorner[t.corner_begin + k];
+  const int bs = blockDim.x;
+  for (int i0 = threadIdx.x; i0 <= t.n_own; i0 += kStageBatch * bs) {
+    int32_t v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) v[u] = dm.lrow[t.node_begin + min(i0 + u * bs, t.n_own)];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (i0 + u * bs <= t.n_own) offs[i0 + u * bs] = uint16_t(v[u] - t.corner_begin);
+  }
+  const int last = t.n_corner - 1;
+  for (int k0 = threadIdx.x; k0 < t.n_corner; k0 += kStageBatch * bs) {
+    uint16_t v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) v[u] = dm.lcorner[t.corner_begin + min(k0 + u * bs, last)];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (k0 + u * bs < t.n_corner) cl[k0 + u * bs] = v[u];
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -543,6 +543,19 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   std::vector<double> geo_all;
   geo_all.reserve(size_t(m->n_te) * 7);
   for (int q = 0; q < 7; ++q) geo_all.insert(geo_all.end(), geo_te[q].begin(), geo_te[q].end());
+  // off-diagonal entries of the element stiffness K^e_kl = A_e grad phi_k . grad phi_l
+  // (pairs 01, 02, 12); the rows of K^e sum to zero, so these three define it
+  const size_t nte_h = size_t(m->n_te);
+  std::vector<double> kw_all(3 * nte_h);
+  for (size_t i = 0; i < nte_h; ++i) {
+    const double A = geo_te[6][i];
+    const double g0x = geo_te[0][i], g0y = geo_te[1][i], g1x = geo_te[2][i], g1y = geo_te[3][i];
+    const double g2x = geo_te[4][i], g2y = geo_te[5][i];
+    kw_all[i] = A * (g0x * g1x + g0y * g1y);
+    kw_all[nte_h + i] = A * (g0x * g2x + g0y * g2y);
+    kw_all[2 * nte_h + i] = A * (g1x * g2x + g1y * g2y);
+  }
+  void* p_kw;
 #define UP(vec, ptr)                                  \
   if ((st = dev_upload(m, vec, &ptr)) != PF_OK) {     \
     free_all(m);                                      \
@@ -557,6 +570,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   UP(te_gid, p_gid);
   if (dtype == PF_F64) to_dtype<double>(geo_all, tmp); else to_dtype<float>(geo_all, tmp);
   UP(tmp, p_geo);
+  if (dtype == PF_F64) to_dtype<double>(kw_all, tmp); else to_dtype<float>(kw_all, tmp);
+  UP(tmp, p_kw);
   UP(lrow, p_lrow);
   UP(lcorner, p_lcorner);
   if (dtype == PF_F64) to_dtype<double>(inv_w, tmp); else to_dtype<float>(inv_w, tmp);
@@ -572,6 +587,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   m->dm.lc2 = static_cast<const uint16_t*>(p_lc2);
   m->dm.te_gid = static_cast<const int32_t*>(p_gid);
   m->dm.geo = p_geo;
+  m->dm.kw = p_kw;
   m->dm.lrow = static_cast<const int32_t*>(p_lrow);
   m->dm.lcorner = static_cast<const uint16_t*>(p_lcorner);
   m->dm.inv_w = p_invw;

@@ -86,6 +86,7 @@ struct DevMesh {
   const uint16_t* lc2;
   const int32_t* te_gid;        // [n_te] internal element id of each tile element
   const void* geo;              // [7][n_te] gx0 gy0 gx1 gy1 gx2 gy2 area (mesh dtype)
+  const void* kw;               // [3][n_te] element stiffness off-diagonals K01 K02 K12 (mesh dtype)
   const int32_t* lrow;          // [N+1] corner list range of each owned node
   const uint16_t* lcorner;      // [sum] tile-local corner id 3*e+k, ascending element id
   const void* inv_w;            // [N] 1 / sum_{e ni i} A_e/3 (mesh dtype)
