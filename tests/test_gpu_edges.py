@@ -1,0 +1,106 @@
+"""Edge cases of the GPU path against the oracle: a one-triangle mesh, the largest
+tile, instances of very different sizes in one handle, a damage solve with every
+node fixed, and an AT1 solve below its threshold (the minimiser is the bound)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle.damage import DamageQP
+from oracle.step import Sim as OSim, run as orun
+from tests.gpu_common import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def one_triangle(seed=0, **kw):
+    h = 2.5e-4
+    r = np.random.default_rng(seed)
+    xy = np.array([[0.0, 0.0], [h, 0.1 * h], [0.2 * h, 0.9 * h]])
+    z = np.zeros((3, 2))
+    return w.small_plate(4, 2, **kw).with_(
+        name="tri1", xy=xy, tri=np.array([[0, 1, 2]], dtype=np.int32), fixed=np.zeros((3, 2), np.uint8),
+        u0=r.normal(size=(3, 2)) * 1e-6, v0=z.copy(), a0=z.copy(), d0=np.zeros(3),
+        H0=np.array([4000.0]))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", [1, 2])
+def test_one_triangle_matches_oracle(dtype, model):
+    from paper_2606_23458_amd import Simulator
+    p = one_triangle(model=model)
+    osim = OSim(p)
+    ref = orun(p, steps=5, sim=osim)[0].numpy()
+    sim = Simulator(p, dtype=dtype, dt=[osim.dt])
+    sim.step(5)
+    torch.cuda.synchronize()
+    got = sim.state.to_user()[0]
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    for f in ("u", "v", "H"):
+        assert rel_err(got[f], ref[f]) < tol, f
+    assert np.max(np.abs(got["d"] - ref["d"])) < tol
+
+
+def test_largest_tile_matches_oracle():
+    """tile_nodes = 2048: the whole plate is one tile (a single workgroup per kernel)."""
+    from paper_2606_23458_amd import Simulator
+    p = w.small_plate(40, 20, jitter=0.1, seed=9)
+    osim = OSim(p)
+    ref = orun(p, steps=20, sim=osim)[0].numpy()
+    sim = Simulator(p, dtype="f64", tile_nodes=2048, dt=[osim.dt])
+    assert sim.mesh.totals.n_tiles == 1
+    sim.step(20)
+    torch.cuda.synchronize()
+    got = sim.state.to_user()[0]
+    for f in ("u", "v", "d", "H"):
+        assert rel_err(got[f], ref[f]) < 1e-9, f
+
+
+def test_instances_of_very_different_sizes_batched_bitwise():
+    from paper_2606_23458_amd import Simulator
+    probs = [one_triangle(seed=1), w.small_plate(30, 15, seed=2), w.small_plate(9, 5, seed=3), one_triangle(seed=4)]
+    both = Simulator(probs, dtype="f64", tile_nodes=128)
+    both.step(10)
+    torch.cuda.synchronize()
+    got = both.state.to_user()
+    for k, pr in enumerate(probs):
+        one = Simulator([pr], dtype="f64", tile_nodes=128, dt=[both.dt[k]])
+        one.step(10)
+        torch.cuda.synchronize()
+        ref = one.state.to_user()[0]
+        for f in ("u", "v", "a", "d", "H"):
+            assert np.array_equal(got[k][f], ref[f]), (k, f)
+
+
+def _solve(p, dtype, H, lb):
+    from paper_2606_23458_amd import Simulator, State
+    sim = Simulator(p, dtype=dtype, tile_nodes=64)
+    st = {"u": np.zeros((p.n_nodes, 2)), "v": np.zeros((p.n_nodes, 2)), "a": np.zeros((p.n_nodes, 2)),
+          "d": lb, "H": H}
+    s_in = State.from_user(sim.mesh, [st])
+    d_out = torch.zeros_like(s_in.d)
+    sim.damage(s_in.H, s_in.d, d_out, sim.active)
+    torch.cuda.synchronize()
+    return sim.mesh.nodes_from_internal(d_out.double())[0], sim.cg_stats()[0]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_every_node_fixed(dtype):
+    """d_prev = 1 everywhere: every node is fixed and the update is 1."""
+    p = w.small_plate(20, 10, seed=4)
+    H = np.random.default_rng(1).uniform(0, 5000, p.n_elems)
+    d, st = _solve(p, dtype, H, np.ones(p.n_nodes))
+    assert np.all(d == 1.0) and st["flags"] == 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_at1_below_threshold_stays_at_the_bound(dtype):
+    """AT1 with H below H_crit = 3 Gc / (16 l0) everywhere and no damage yet: the
+    minimiser is the lower bound 0 (the AT1 elastic stage, Sec. 2.1)."""
+    p = w.small_plate(20, 10, seed=5, model=1).with_(d0=np.zeros(231))
+    hc = 3 * p.Gc / (16 * p.l0)
+    H = np.random.default_rng(2).uniform(0, 0.9 * hc, p.n_elems)
+    d, st = _solve(p, dtype, H, np.zeros(p.n_nodes))
+    ref = DamageQP(OSim(p).mesh, p.l0, 1).solve(H, p.Gc, np.zeros(p.n_nodes))[0]
+    assert np.all(ref == 0.0)
+    assert np.all(d == 0.0) and st["flags"] == 0
