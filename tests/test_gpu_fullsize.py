@@ -31,7 +31,8 @@ def _sim(problem, dtype, **kw):
 def full(request):
     p = {"c1": w.config1, "c2": w.config2}[request.param]()
     osim = OSim(p)
-    sim = _sim(p, "f32", dt=[osim.dt])
+    # the autotuned tile plan, as bench.py times it
+    sim = _sim(p, "f32", dt=[osim.dt], tile_nodes="auto")
     return request.param, p, osim, sim
 
 
@@ -89,3 +90,31 @@ def test_batched_equals_plain_bitwise():
         ref = one.state.to_user()[0]
         for f in ("u", "v", "a", "d", "H"):
             assert np.array_equal(got[k][f], ref[f]), (k, f)
+
+
+def test_full_length_run_properties(full):
+    """The configured step count (1000 for the 1024x512 plate, 500 for the perforated one) with
+    windowed stepping: every solve converges, 0 <= d <= 1, d and H never decrease, and the last
+    damage update satisfies the KKT conditions of its programme (FP64, oracle operator)."""
+    from paper_2606_23458_amd import State
+    name, p, osim, sim = full
+    sim.reset()
+    half = p.steps // 2
+    sim.run(half)
+    mid = sim.state.to_user()[0]
+    sim.run(p.steps - half - 1)
+    prev = sim.state.clone()
+    s_out = State(sim.mesh)
+    act = torch.zeros_like(sim.active)
+    sim.step_into(prev, s_out, act, sim.active)
+    torch.cuda.synchronize()
+    assert sim.cg_stats()[0]["flags"] == 0
+    end = s_out.to_user()[0]
+    lb = prev.to_user()[0]["d"]
+    assert np.all(np.isfinite(end["u"])) and np.all(np.isfinite(end["v"]))
+    assert np.all(end["d"] >= 0.0) and np.all(end["d"] <= 1.0)
+    assert np.all(end["d"] >= mid["d"]) and np.all(end["H"] >= mid["H"]), name
+    A, b = osim.qp.system(end["H"], p.Gc)
+    viol, rf, ra, ru = kkt_residuals(A, b, lb, end["d"], np.ones_like(lb))
+    assert viol <= 0 and rf < 5e-6 and ra < 5e-6 and ru < 5e-6, (name, rf, ra, ru)
+    assert end["d"].max() > 0.5, "the crack has started to grow"
