@@ -8,12 +8,18 @@ strain), reported as element-steps per second with inputs resident in HBM.
 Also reported on the same JSON line:
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 average launch time (HIP events around each launch);
-  cpu_baseline  the FP64 CPU oracle on one staggered step of the same plate;
+  cpu_baseline  the FP64 CPU oracle on the first two staggered steps of the
+                same plate;
   bwd_fwd       backward/forward time of the checkpointed gradient on the
                 256x128 FP64 plate (500 steps, checkpoints every 50);
   batched       simulations/s of one batched forward+backward evaluation of
                 the 64-plate inverse workload vs the same 64 evaluations one
-                plate at a time.
+                plate at a time;
+and, unless --no-extras: the explicit step alone, polled and graph-replayed
+stepping, damage subcycling, the toughness field, the energy kernel, the
+preconditioners, and the explicit step and CG pass on a 2048x1024 plate that
+does not fit the Infinity Cache.  The tile plan is the autotuner's unless
+--tile-nodes fixes it.
 """
 from __future__ import annotations
 
