@@ -168,6 +168,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[8 * kWaves];
   const int tile = tile_of_block(a.dm.n_tiles);
   const TileRec t = a.dm.tiles[tile];
+  // the corner lists do not depend on the solver state: their loads go first
+  StagedCorners<2, 12> scn;   // 256 threads: 512 offsets, 3072 corner ids in registers
+  stage_corners_load(a.dm, t, scn);
   const Ctl* c = a.ctl + t.inst;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
@@ -218,7 +221,6 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   T* bc = dc;                                  // [chunk] from offset 3 chunk: load per corner (set-up)
   const int tid = threadIdx.x;
 
-  stage_corners(a.dm, t, coffs, clist);
 
   // Chebyshev coefficients of this pass's step (the main pass makes step 1)
   ChebCoef chc{1.0, 0.0, 0.0};
@@ -228,7 +230,68 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
 
   // ---- phase 1: the vector to multiply, on owned and halo nodes -------------
   double amin = INFINITY, ch = 0.0;
-  for (int i = tid; i < nloc; i += kBlock) {
+  // first / iterate main passes: every owned-node load is issued before any
+  // update, and r, D^-1 and the held flag stay in registers for phase 3
+  const bool fast = !xpass && stage == 0;
+  T rz_r[NPT], di_r[NPT];
+  uint8_t wf_r[NPT];
+  if (fast) {
+    T rv_r[NPT], wc_r[NPT], sc_r[NPT], p_r[NPT], x_r[NPT], zb_r[NPT], lb_r[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int i = tid + r * kBlock;
+      const int g = t.node_begin + min(i, t.n_own - 1);
+      wf_r[r] = Wc[g];
+      di_r[r] = a.dinv[g];
+      rv_r[r] = rc[g];
+      if (iter) {
+        wc_r[r] = wc[g];
+        sc_r[r] = (beta == 0.0) ? T(0) : sc[g];
+        p_r[r] = (beta == 0.0) ? T(0) : a.p[g];
+        x_r[r] = xc[g];
+        zb_r[r] = CHEB ? a.zb[g] : T(0);
+        lb_r[r] = projected ? a.lb[g] : T(0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int i = tid + r * kBlock;
+      if (i >= t.n_own) continue;
+      const int g = t.node_begin + i;
+      const uint8_t wf = wf_r[r];
+      const T di = di_r[r];
+      const T rv = rv_r[r];
+      T v;
+      if (!iter) {
+        v = wf ? T(0) : (CHEB ? di * rv * ith : di * rv);
+        rz_r[r] = rv;
+      } else {
+        const T sn = (beta == 0.0) ? wc_r[r] : wc_r[r] + be * sc_r[r];
+        const T rn = rv - al * sn;
+        v = wf ? T(0) : (CHEB ? di * rn * ith : di * rn);
+        const T zv = wf ? T(0) : (CHEB ? zb_r[r] : di * rv);
+        const T pv = (beta == 0.0) ? zv : zv + be * p_r[r];
+        const T xv = x_r[r];
+        T xn = xv + al * pv;
+        if (monotone && !wf) {
+          const double lbv = double(lb_r[r]);
+          if (pv < T(0)) amin = fmin(amin, (lbv - double(xv)) / double(pv));
+          if (pv > T(0)) amin = fmin(amin, (1.0 - double(xv)) / double(pv));
+          xn = clamp01<T>(xn, T(lbv));
+        } else if (projected && !wf) {
+          const double xd = double(xn);
+          if (double(lb_r[r]) - xd > tol || xd - 1.0 > tol) ch += 1.0;
+        }
+        a.p[g] = pv;
+        sn_[g] = sn;
+        xn_[g] = xn;
+        rn_[g] = rn;
+        rz_r[r] = rn;
+      }
+      sv[i] = v;
+    }
+  }
+  for (int i = fast ? t.n_own + tid : tid; i < nloc; i += kBlock) {
     const bool own = i < t.n_own;
     const int g = own ? t.node_begin + i : a.dm.halo_idx[t.halo_begin + (i - t.n_own)];
     T v;
@@ -290,6 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     }
     sv[i] = v;
   }
+  stage_corners_store(a.dm, t, scn, coffs, clist);
 
   // ---- set-up: load vector, Jacobi diagonal, per-solve mass coefficients ----
   // The space after sv holds the corner values of one pass; restart and check
@@ -486,22 +550,25 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     T* wn = iter ? wn_ : (cur1 ? a.w1 : a.w0);
     const T* rz = iter ? rn_ : rc;
     T* ydst = (stage & 1) ? a.y1 : a.y0;
-    for (int i = tid; i < t.n_own; i += kBlock) {
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int i = tid + r * kBlock;
+      if (i >= t.n_own) continue;
       const int g = t.node_begin + i;
       const int j0 = coffs[i], j1 = coffs[i + 1];
       T qi = T(0);
       for (int j = j0; j < j1; ++j) qi += qc[clist[j]];
       if (CHEB && stage < a.cheb - 1) {
         // Chebyshev step stage + 1: qi = A y_j; d_j and y_{j+1} = y_j + d_j (0 on held nodes)
-        const uint8_t w = Wc[g];
-        const T rv = rz[g];
+        const uint8_t w = fast ? wf_r[r] : Wc[g];
+        const T rv = fast ? rz_r[r] : rz[g];
         const T yv = sv[i];
-        const T res = a.dinv[g] * (rv - qi);
+        const T res = (fast ? di_r[r] : a.dinv[g]) * (rv - qi);
         const T dj = w ? T(0) : T(chc.c1) * (stage == 0 ? yv : a.dv[g]) + T(chc.c2) * res;
         ydst[g] = w ? T(0) : yv + dj;
         a.dv[g] = dj;
         if (stage == 0) {
-          const double sr = double(rv) * double(a.dinv[g]);
+          const double sr = double(rv) * double(di_r[r]);
           if (w) {
             if (w != HELD_FIXED) ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
           } else {
@@ -514,18 +581,18 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       if (CHEB) {
         // the A z pass: z = y_cheb, w = A z; the stopping partials came from the main pass
         const T zv = sv[i];
-        const T rv = rz[g];
+        const T rv = rz[g];   // a later pass of the round: r is read back
         a.zb[g] = zv;
         gam += double(rv) * double(zv);
         del += double(zv) * double(qi);
         continue;
       }
       const T zv = sv[i];
-      const T rv = rz[g];
+      const T rv = rz_r[r];   // non-Chebyshev first / iterate passes are main passes
       gam += double(rv) * double(zv);
       del += double(zv) * double(qi);
-      const double sr = double(rv) * double(a.dinv[g]);
-      const uint8_t w = Wc[g];
+      const double sr = double(rv) * double(di_r[r]);
+      const uint8_t w = wf_r[r];
       if (w) {
         if (w != HELD_FIXED) ca = fmax(ca, w == HELD_UPPER ? -sr : sr);
       } else {

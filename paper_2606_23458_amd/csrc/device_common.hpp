@@ -50,6 +50,45 @@ __device__ __forceinline__ int tile_of_block(int n_tiles) {
 // index node i's entries of cl, which are tile-local corner ids 3 e + k in
 // ascending element id.  Coalesced loads by the whole block; the caller
 // synchronises before reading.
+// Split staging: the loads of a tile's corner lists are issued into registers
+// at kernel entry (NR row offsets and NC corner ids per thread) and stored to
+// LDS later, so their latency overlaps the first phase's own loads; entries
+// beyond the register capacity (large tiles) are copied at store time.
+template <int NR, int NC>
+struct StagedCorners {
+  int32_t off[NR];
+  uint16_t c[NC];
+};
+
+template <int NR, int NC>
+__device__ __forceinline__ void stage_corners_load(const DevMesh& dm, const TileRec& t, StagedCorners<NR, NC>& s) {
+  const int bs = blockDim.x;
+#pragma unroll
+  for (int u = 0; u < NR; ++u) s.off[u] = dm.lrow[t.node_begin + min(int(threadIdx.x) + u * bs, t.n_own)];
+  const int last = t.n_corner - 1;   // every owned node has at least one corner
+#pragma unroll
+  for (int u = 0; u < NC; ++u) s.c[u] = dm.lcorner[t.corner_begin + min(int(threadIdx.x) + u * bs, last)];
+}
+
+template <int NR, int NC>
+__device__ __forceinline__ void stage_corners_store(const DevMesh& dm, const TileRec& t,
+                                                    const StagedCorners<NR, NC>& s, uint16_t* offs, uint16_t* cl) {
+  const int bs = blockDim.x;
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int i = threadIdx.x + u * bs;
+    if (i <= t.n_own) offs[i] = uint16_t(s.off[u] - t.corner_begin);
+  }
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int k = threadIdx.x + u * bs;
+    if (k < t.n_corner) cl[k] = s.c[u];
+  }
+  for (int i = threadIdx.x + NR * bs; i <= t.n_own; i += bs)
+    offs[i] = uint16_t(dm.lrow[t.node_begin + i] - t.corner_begin);
+  for (int k = threadIdx.x + NC * bs; k < t.n_corner; k += bs) cl[k] = dm.lcorner[t.corner_begin + k];
+}
+
 // Each thread issues the loads of kStageBatch entries before it stores any of
 // them, so a tile's lists arrive in a few memory round trips rather than one
 // per block-wide stride (indices past the end are clamped to the last entry).

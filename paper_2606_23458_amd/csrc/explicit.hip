@@ -33,7 +33,9 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   uint16_t* coffs = reinterpret_cast<uint16_t*>(sfy + 3 * chs);         // [n_own + 1] corner-list offsets
   uint16_t* clist = coffs + t.n_own + 1;                                // [n_corner] corner ids
   const int tid = threadIdx.x;
-  stage_corners(dm, t, coffs, clist);
+  // corner-list loads first (registers), stored to LDS after the predictor
+  StagedCorners<(BS == 256 ? 2 : 1), (BS == 256 ? 12 : 6)> scn;
+  stage_corners_load(dm, t, scn);
 
   // ---- phase 1: predictor (eq. vv_u) -------------------------------------
   T rvx[NPT], rvy[NPT], rax[NPT], ray[NPT];
@@ -59,6 +61,7 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
     suy[i] = in.uy[g] + P.dt * in.vy[g] + P.half_dt2 * in.ay[g];
     sd[i] = in.d[g];
   }
+  stage_corners_store(dm, t, scn, coffs, clist);
   __syncthreads();
 
   // ---- phases 2 and 3a, per chunk of elements ------------------------------
