@@ -339,12 +339,13 @@ pf_status_t pf_subcycle_limit(pf_mesh_t m, const pf_params_t* p, int32_t* n_max_
  * Tile-size autotuning (a set-up call, not part of the method; it allocates).
  * For each candidate owned-node count per tile it builds the tile plan of the
  * given meshes, times `reps` explicit steps from a zero state (with 256- and
- * with 512-thread workgroups, keeping the faster) and `reps` damage CG rounds
- * (the launches of one CG iteration, on a linear solve over all nodes), and
- * scores the plan as
+ * with 512-thread workgroups, each with its elements in one and in two
+ * chunks, keeping the fastest) and `reps` damage CG rounds (the launches of
+ * one CG iteration, on a linear solve over all nodes), and scores the plan as
  *     explicit_us + cg_rounds_per_step * cg_round_us.
- * The smallest score wins; pass out->best and out->best_explicit_block as
- * pf_tile_opts_t.tile_nodes and .explicit_block.
+ * The smallest score wins; pass out->best, out->best_explicit_block and
+ * out->best_explicit_chunks as pf_tile_opts_t.tile_nodes, .explicit_block
+ * and .explicit_chunks.
  * Candidates whose tiles need more LDS than a workgroup may use are skipped
  * (status PF_ERR_UNSUPPORTED).  `inst`, `n_instances`, `dtype` and `p` are as
  * for pf_mesh_create and pf_explicit_step.  Synchronous on `stream`; the
