@@ -120,7 +120,10 @@ typedef struct {
                                 no node held at a bound has a scaled residual
                                 r_i/A_ii pointing inward by more than tol/4
                                 (held nodes beyond that are released) */
-    int32_t max_iter;        /* matrix-vector products per solve, >= 1 */
+    int32_t max_iter;        /* CG rounds per solve, >= 1 (a round is one pass
+                                over the tiles and one reduction; with the
+                                Jacobi preconditioner one matrix-vector
+                                product) */
     int32_t check_every;     /* > 0: synchronise the stream to stop early: first
                                 after as many CG rounds as the handle's previous
                                 solve of the same kind needed (8 on the first
