@@ -165,7 +165,7 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
 
 template <typename T, int NPT, bool CHEB>
 __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
-  __shared__ double red[8 * kWaves];
+  __shared__ double red[8 * 4 * kWaves];
   const int tile = tile_of_block(a.dm.n_tiles);
   const TileRec t = a.dm.tiles[tile];
   // the corner lists do not depend on the solver state: their loads go first
@@ -610,20 +610,18 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     store = (stage == 0) ? (0xffu & ~gd) : gd;
   }
   double v[8] = {del, amin, gam, cf, ca, na, rb, ch};   // in PT_* order
-  block_reduce_to0<8, kPartOps>(v, red);
-  // partials are stored value-major, [8][n_tiles], so the reduction reads them coalesced
-  if (tid == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (store & (1u << k)) a.part[size_t(k) * a.dm.n_tiles + tile] = v[k];
-  }
+  const double tot = block_reduce_rows<8, kPartOps>(v, red);
+  // partials are stored value-major, [8][n_tiles], so the reduction reads them
+  // coalesced; thread k holds value k
+  if (tid < 8 && (store & (1u << tid))) a.part[size_t(tid) * a.dm.n_tiles + tile] = tot;
 }
 
 // One workgroup per instance: combine the tiles' partials and advance the state.
 constexpr int kRedBlock = kBlock;
 __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* part, int n_tiles, const int* bounds,
                                                        int kind, double tol, int max_iter) {
-  __shared__ double red[8 * (kRedBlock / 64)];
+  __shared__ double red[8 * 4 * (kRedBlock / 64)];
+  __shared__ double tot[8];
   Ctl* c = ctl + blockIdx.x;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
@@ -640,8 +638,12 @@ __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* p
     v[PT_RB] = fmax(v[PT_RB], part[PT_RB * nt + k]);
     v[PT_CH] += part[PT_CH * nt + k];
   }
-  block_reduce_to0<8, kPartOps, kRedBlock / 64>(v, red);
+  const double vk = block_reduce_rows<8, kPartOps, kRedBlock / 64>(v, red);
+  if (threadIdx.x < 8) tot[threadIdx.x] = vk;
+  __syncthreads();
   if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = tot[k];
   const double sdel = v[PT_DELTA], samin = v[PT_AMIN], sgam = v[PT_GAMMA], scf = v[PT_CF], sca = v[PT_CA];
   const double sna = v[PT_NA], srb = v[PT_RB], sch = v[PT_CH];
   const bool qp = (kind == CG_QP);

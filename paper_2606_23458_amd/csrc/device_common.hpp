@@ -202,4 +202,72 @@ __device__ __forceinline__ void block_reduce_to0(double (&v)[K], double* sh) {
   }
 }
 
+// Lane moves within 16-lane rows (DPP controls of the GFX9 family): swap
+// neighbours, swap pairs, mirror each half-row, mirror the row.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within each 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within each 16 lanes
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(x));
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(
+      static_cast<long long>((static_cast<unsigned long long>(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+__device__ __forceinline__ double combine_op(uint32_t op, double s, double y) {
+  return op == 0 ? s + y : (op == 1 ? fmin(s, y) : fmax(s, y));
+}
+
+// Reduce x over each 16-lane row: after the four steps every lane of a row
+// holds the row's result (each step combines a lane with its mirror image, so
+// both compute the same operation on the same pair).  All 64 lanes must be
+// active.
+template <uint32_t OP>
+__device__ __forceinline__ double row_reduce(double x) {
+  x = combine_op(OP, x, dpp_move<kDppXor1>(x));
+  x = combine_op(OP, x, dpp_move<kDppXor2>(x));
+  x = combine_op(OP, x, dpp_move<kDppHalfMirror>(x));
+  x = combine_op(OP, x, dpp_move<kDppMirror>(x));
+  return x;
+}
+
+template <int K, uint32_t OPS, int k = 0>
+__device__ __forceinline__ void row_reduce_all(double (&v)[K]) {
+  if constexpr (k < K) {
+    v[k] = row_reduce<(OPS >> (2 * k)) & 3u>(v[k]);
+    row_reduce_all<K, OPS, k + 1>(v);
+  }
+}
+
+// Several block-wide reductions at once, without LDS shuffles: each value is
+// reduced over every 16-lane row by DPP moves, lane 0 of each row stores the
+// row's results, and thread k < K combines value k's 4 NW row results in a
+// fixed order and returns it (other threads get 0).  OPS holds two bits per
+// value: 0 sum, 1 min, 2 max.  Every thread of the block must call it; `sh`
+// holds K * 4 * NW doubles and must not be in use by another reduction of the
+// block.
+template <int K, uint32_t OPS, int NW = kWaves>
+__device__ __forceinline__ double block_reduce_rows(double (&v)[K], double* sh) {
+  constexpr int R = 4 * NW;
+  row_reduce_all<K, OPS>(v);
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == 0) {
+    const int r = (threadIdx.x >> 6) * 4 + (lane >> 4);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * R + r] = v[k];
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k >= K) return 0.0;
+  const uint32_t op = (OPS >> (2 * k)) & 3u;
+  double s = sh[k * R];
+#pragma unroll
+  for (int j = 1; j < R; ++j) s = combine_op(op, s, sh[k * R + j]);
+  return s;
+}
+
 }  // namespace pf
