@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
                                                        const T* __restrict__ dbar, const T* __restrict__ hbar_in,
                                                        const uint8_t* __restrict__ W, T* hbar, T* dprev_bar,
                                                        double* dgc_field) {
-  __shared__ double red[kWaves];
+  __shared__ double red[4 * kWaves];
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
 
 // One workgroup per instance: dGc += the instance's tile partials, fixed order.
 __global__ __launch_bounds__(kBlock) void k_adj_reduce(const Ctl* ctl, const double* part, int n_tiles, double* dGc) {
-  __shared__ double red[kWaves];
+  __shared__ double red[4 * kWaves];
   const Ctl* c = ctl + blockIdx.x;
   double s = 0.0;
   const double* p7 = part + size_t(7) * n_tiles + c->tile0;

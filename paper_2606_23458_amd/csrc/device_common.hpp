@@ -1,6 +1,6 @@
-// Device helpers shared by the kernels: state pointer bundles and
-// deterministic block reductions (wave64 butterflies, then a fixed-order
-// combine of the four waves).
+// Device helpers shared by the kernels: state pointer bundles, the tile map,
+// corner-list staging and deterministic block reductions (DPP lane moves
+// within 16-lane rows, then a fixed-order combine of the block's rows).
 #pragma once
 
 #include "pf_internal.hpp"
@@ -114,94 +114,6 @@ __device__ __forceinline__ void stage_corners(const DevMesh& dm, const TileRec& 
   }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Block-wide reductions; every thread gets the result.  `sh` holds kWaves doubles.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double s = sh[0];
-#pragma unroll
-  for (int k = 1; k < kWaves; ++k) s += sh[k];
-  return s;
-}
-
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  v = wave_max(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double s = sh[0];
-#pragma unroll
-  for (int k = 1; k < kWaves; ++k) s = fmax(s, sh[k]);
-  return s;
-}
-
-__device__ __forceinline__ double block_min(double v, double* sh) {
-  v = wave_min(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double s = sh[0];
-#pragma unroll
-  for (int k = 1; k < kWaves; ++k) s = fmin(s, sh[k]);
-  return s;
-}
-
-// Several block-wide reductions at once, with one barrier: every wave
-// reduces each value by shuffles, lane 0 of each wave stores its results, and
-// thread 0 combines the waves in a fixed order (only thread 0's v holds the
-// block result).  OPS holds two bits per value: 0 sum, 1 min, 2 max.  NW is
-// the block's wave count; `sh` holds K * NW doubles and must not be in use by
-// another reduction of the block.
-template <int K, uint32_t OPS, int NW = kWaves>
-__device__ __forceinline__ void block_reduce_to0(double (&v)[K], double* sh) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint32_t op = (OPS >> (2 * k)) & 3u;
-    v[k] = op == 0 ? wave_sum(v[k]) : (op == 1 ? wave_min(v[k]) : wave_max(v[k]));
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) sh[k * NW + w] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint32_t op = (OPS >> (2 * k)) & 3u;
-    double s = sh[k * NW];
-#pragma unroll
-    for (int j = 1; j < NW; ++j) {
-      const double y = sh[k * NW + j];
-      s = op == 0 ? s + y : (op == 1 ? fmin(s, y) : fmax(s, y));
-    }
-    v[k] = s;
-  }
-}
-
 // Lane moves within 16-lane rows (DPP controls of the GFX9 family): swap
 // neighbours, swap pairs, mirror each half-row, mirror the row.
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
@@ -268,6 +180,44 @@ __device__ __forceinline__ double block_reduce_rows(double (&v)[K], double* sh) 
 #pragma unroll
   for (int j = 1; j < R; ++j) s = combine_op(op, s, sh[k * R + j]);
   return s;
+}
+
+// Block-wide sum; every thread gets the result.  `sh` holds 4 kWaves doubles
+// (one per 16-lane row); the rows' sums are added in a fixed order.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = row_reduce<0u>(v);
+  const int lane = threadIdx.x & 63;
+  __syncthreads();   // sh may still be read by a previous reduction
+  if ((lane & 15) == 0) sh[(threadIdx.x >> 6) * 4 + (lane >> 4)] = v;
+  __syncthreads();
+  double s = sh[0];
+#pragma unroll
+  for (int j = 1; j < 4 * kWaves; ++j) s += sh[j];
+  return s;
+}
+
+// Several block-wide reductions at once; only thread 0's v holds the block
+// results afterwards.  Same scheme and arguments as block_reduce_rows.
+template <int K, uint32_t OPS, int NW = kWaves>
+__device__ __forceinline__ void block_reduce_to0(double (&v)[K], double* sh) {
+  constexpr int R = 4 * NW;
+  row_reduce_all<K, OPS>(v);
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == 0) {
+    const int r = (threadIdx.x >> 6) * 4 + (lane >> 4);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * R + r] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t op = (OPS >> (2 * k)) & 3u;
+    double t = sh[k * R];
+#pragma unroll
+    for (int j = 1; j < R; ++j) t = combine_op(op, t, sh[k * R + j]);
+    v[k] = t;
+  }
 }
 
 }  // namespace pf

@@ -19,7 +19,7 @@ namespace pf {
 template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_energy(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> st,
                                                    double* part) {
-  __shared__ double red[3 * kWaves];
+  __shared__ double red[3 * 4 * kWaves];
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(DevMesh dm, const InstP<T>* _
 // One workgroup per instance: fixed-order sums of the tiles' partials.
 __global__ __launch_bounds__(kBlock) void k_energy_reduce(const Ctl* ctl, const double* part, int n_tiles,
                                                           double* out) {
-  __shared__ double red[3 * kWaves];
+  __shared__ double red[3 * 4 * kWaves];
   const Ctl* c = ctl + blockIdx.x;
   double v[3] = {0.0, 0.0, 0.0};
   for (int k = c->tile0 + threadIdx.x; k < c->tile0 + c->ntiles; k += kBlock) {
