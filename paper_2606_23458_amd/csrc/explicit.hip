@@ -36,14 +36,31 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   // corner-list loads first (registers), stored to LDS after the predictor
   StagedCorners<(BS == 256 ? 2 : 1), (BS == 256 ? 12 : 6)> scn;
   stage_corners_load(dm, t, scn);
+  // so is each thread's first element record (clamped on threads past the end)
+  const T* __restrict__ geo = static_cast<const T*>(dm.geo);
+  const size_t nte = size_t(dm.n_te);
+  const int pte = t.telem_begin + min(tid, t.n_telem - 1);
+  const int pc0 = dm.lc0[pte], pc1 = dm.lc1[pte], pc2 = dm.lc2[pte];
+  T pg[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) pg[k] = geo[size_t(k) * nte + pte];
 
   // ---- phase 1: predictor (eq. vv_u) -------------------------------------
-  T rvx[NPT], rvy[NPT], rax[NPT], ray[NPT];
+  // the corrector's inputs (lumped mass, prescribed flags, external force)
+  // are loaded here too, so that the last phase waits on no memory
+  const T* __restrict__ invw = static_cast<const T*>(dm.inv_w);
+  const size_t N = size_t(dm.n_nodes);
+  T rvx[NPT], rvy[NPT], rax[NPT], ray[NPT], rmi[NPT], rex[NPT], rey[NPT];
+  uint8_t rfl[NPT];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int i = tid + r * BS;
     if (i < t.n_own) {
       const int g = t.node_begin + i;
+      rmi[r] = invw[g];
+      rfl[r] = dm.fixed[g];
+      rex[r] = fext ? fext[g] : T(0);
+      rey[r] = fext ? fext[N + g] : T(0);
       const T vx = in.vx[g], vy = in.vy[g], ax = in.ax[g], ay = in.ay[g];
       const T usx = in.ux[g] + P.dt * vx + P.half_dt2 * ax;
       const T usy = in.uy[g] + P.dt * vy + P.half_dt2 * ay;
@@ -65,8 +82,6 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   __syncthreads();
 
   // ---- phases 2 and 3a, per chunk of elements ------------------------------
-  const T* __restrict__ geo = static_cast<const T*>(dm.geo);
-  const size_t nte = size_t(dm.n_te);
   T fxa[NPT], fya[NPT];
   int jc[NPT];   // next corner of each owned node
 #pragma unroll
@@ -79,11 +94,7 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   const int e1 = min(e0 + chs, t.n_telem);
   if (e0 > 0) __syncthreads();   // the previous chunk's corner forces have been added
   // phase 2: element strain, split, stress, corner forces, history
-  for (int e = e0 + tid; e < e1; e += BS) {
-    const int te = t.telem_begin + e;
-    const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
-    const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-    const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+  auto element = [&](int e, int c0, int c1, int c2, T g0x, T g0y, T g1x, T g1y, T g2x, T g2y, T A) {
     const T u0x = sux[c0], u0y = suy[c0], u1x = sux[c1], u1y = suy[c1], u2x = sux[c2], u2y = suy[c2];
     T exx, eyy, exy;
     elem_strain<T>(u0x, u0y, u1x, u1y, u2x, u2y, g0x, g0y, g1x, g1y, g2x, g2y, exx, eyy, exy);
@@ -105,6 +116,17 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
       const T Hn = in.H[gid];
       out.H[gid] = psi_p > Hn ? psi_p : Hn;
     }
+  };
+  int e = e0 + tid;
+  if (e0 == 0 && e < e1) {
+    // this thread's first element, loaded at kernel entry
+    element(e, pc0, pc1, pc2, pg[0], pg[1], pg[2], pg[3], pg[4], pg[5], pg[6]);
+    e += BS;
+  }
+  for (; e < e1; e += BS) {
+    const int te = t.telem_begin + e;
+    element(e, dm.lc0[te], dm.lc1[te], dm.lc2[te], geo[te], geo[nte + te], geo[2 * nte + te], geo[3 * nte + te],
+            geo[4 * nte + te], geo[5 * nte + te], geo[6 * nte + te]);
   }
   __syncthreads();
   // phase 3a: each owned node adds the corners of this chunk, in list order
@@ -129,18 +151,16 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   }
 
   // ---- phase 3b: corrector (eq. vv_a, eq. vv_v) ----------------------------
-  const T* __restrict__ invw = static_cast<const T*>(dm.inv_w);
-  const size_t N = size_t(dm.n_nodes);
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int i = tid + r * BS;
     if (i < t.n_own) {
       const int g = t.node_begin + i;
       const T fx = fxa[r], fy = fya[r];
-      const T minv = P.inv_rho * invw[g];
-      const uint8_t fl = dm.fixed[g];
-      const T ex = fext ? fext[g] : T(0);
-      const T ey = fext ? fext[N + g] : T(0);
+      const T minv = P.inv_rho * rmi[r];
+      const uint8_t fl = rfl[r];
+      const T ex = rex[r];
+      const T ey = rey[r];
       const T axn = (fl & 1) ? T(0) : minv * (ex - fx);
       const T ayn = (fl & 2) ? T(0) : minv * (ey - fy);
       out.vx[g] = rvx[r] + P.half_dt * (rax[r] + axn);
