@@ -36,7 +36,9 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
   // corner-list loads first (registers), stored to LDS after the predictor
   StagedCorners<(BS == 256 ? 2 : 1), (BS == 256 ? 12 : 6)> scn;
   stage_corners_load(dm, t, scn);
-  // so is each thread's first element record (clamped on threads past the end)
+  // so are each thread's first halo node id and first element record
+  // (clamped on threads past the end)
+  const int hg0 = t.n_halo > 0 ? dm.halo_idx[t.halo_begin + min(tid, t.n_halo - 1)] : t.node_begin;
   const T* __restrict__ geo = static_cast<const T*>(dm.geo);
   const size_t nte = size_t(dm.n_te);
   const int pte = t.telem_begin + min(tid, t.n_telem - 1);
@@ -72,12 +74,13 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
       rvx[r] = vx, rvy[r] = vy, rax[r] = ax, ray[r] = ay;
     }
   }
-  for (int i = t.n_own + tid; i < nloc; i += BS) {
-    const int g = dm.halo_idx[t.halo_begin + (i - t.n_own)];
+  auto halo = [&](int i, int g) {
     sux[i] = in.ux[g] + P.dt * in.vx[g] + P.half_dt2 * in.ax[g];
     suy[i] = in.uy[g] + P.dt * in.vy[g] + P.half_dt2 * in.ay[g];
     sd[i] = in.d[g];
-  }
+  };
+  if (tid < t.n_halo) halo(t.n_own + tid, hg0);
+  for (int i = t.n_own + BS + tid; i < nloc; i += BS) halo(i, dm.halo_idx[t.halo_begin + (i - t.n_own)]);
   stage_corners_store(dm, t, scn, coffs, clist);
   __syncthreads();
 
