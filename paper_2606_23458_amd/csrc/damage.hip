@@ -53,6 +53,8 @@
 // other, so halo reads never race with the owners' writes.  No atomics and no
 // device-wide fences are used.  Linear mode (CG_LINEAR) solves A_FF x_F = b_F
 // for a fixed held set and is used by the adjoint step.
+#include <cstring>
+
 #include "device_common.hpp"
 
 namespace pf {
@@ -863,6 +865,11 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
                                : (npt <= 2 ? k_dmg<T, 2, true> : (npt <= 4 ? k_dmg<T, 4, true> : k_dmg<T, 8, true>)))
                    : (npt <= 1 ? k_dmg<T, 1, false>
                                : (npt <= 2 ? k_dmg<T, 2, false> : (npt <= 4 ? k_dmg<T, 4, false> : k_dmg<T, 8, false>)));
+  if (kind == CG_QP) {
+    const unsigned char* ab = reinterpret_cast<const unsigned char*>(&a);
+    m->last_qp_args.assign(ab, ab + sizeof(a));
+    m->last_qp_cheb = a.cheb;
+  }
   auto round = [&]() {
     // one pass, or with the Chebyshev preconditioner one pass per matrix-vector product
     for (int st = 0; st < (cheb ? a.cheb : 1); ++st) {
@@ -928,6 +935,29 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
   return PF_OK;
 }
 
+// n launches of the main pass of the last damage solve's current round, with
+// no reduction in between (a throughput measurement; see pf.h).
+template <typename T>
+static pf_status_t repeat_pass(pf_mesh_s* m, int n, hipStream_t s) {
+  DmgArgs<T> a;
+  if (m->last_qp_args.size() != sizeof(a)) return fail(PF_ERR_ARG, "no damage solve on this handle");
+  if (m->last_qp_cheb != 0) return fail(PF_ERR_ARG, "repeated passes need the Jacobi preconditioner");
+  std::memcpy(&a, m->last_qp_args.data(), sizeof(a));
+  PF_HIP(hipMemcpyAsync(m->ctl_pinned, m->dw.ctl, sizeof(Ctl) * m->n_inst, hipMemcpyDeviceToHost, s));
+  PF_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < m->n_inst; ++k)
+    if (m->ctl_pinned[k].mode != MODE_ITER)
+      return fail(PF_ERR_ARG, "the last damage solve did not stop in a CG iteration");
+  const int npt = (m->max_own + kBlock - 1) / kBlock;
+  auto kdmg = npt <= 1 ? k_dmg<T, 1, false>
+                       : (npt <= 2 ? k_dmg<T, 2, false> : (npt <= 4 ? k_dmg<T, 4, false> : k_dmg<T, 8, false>));
+  a.stage = 0;
+  for (int i = 0; i < n; ++i)
+    hipLaunchKernelGGL(kdmg, dim3(m->n_tiles), dim3(kBlock), m->max_lds_damage, s, a);
+  PF_HIP(hipGetLastError());
+  return PF_OK;
+}
+
 pf_status_t damage_cg(pf_mesh_s* m, int kind, const void* H, const void* lb, void* x, const uint8_t* guess,
                       uint8_t* active_out, const pf_cg_opts_t* o, pf_cg_stats_t* stats, hipStream_t s) {
   return (m->dtype == PF_F64) ? run_solve<double>(m, kind, H, lb, x, guess, active_out, o, stats, s)
@@ -954,4 +984,11 @@ extern "C" pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const 
   if ((st = upload_params(m, p, nullptr, s)) != PF_OK) return st;
   m->qp_started = true;
   return damage_cg(m, CG_QP, H, d_prev, d, active_guess, active_out, opts, stats, s);
+}
+
+extern "C" pf_status_t pf_damage_pass_repeat(pf_mesh_t m, int32_t n_passes, pf_stream_t stream) {
+  if (!m) return fail(PF_ERR_ARG, "mesh is NULL");
+  if (n_passes < 1) return fail(PF_ERR_ARG, "n_passes must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return (m->dtype == PF_F64) ? repeat_pass<double>(m, n_passes, s) : repeat_pass<float>(m, n_passes, s);
 }

@@ -150,6 +150,8 @@ struct pf_mesh_s {
   std::vector<double> dt_cache;      // dt of the last explicit step (the damage solve reuses it)
   int32_t last_rounds[2] = {0, 0};   // CG rounds the last solve of each kind needed (sets the first poll)
   bool qp_started = false;           // a damage solve has been enqueued (resume is allowed)
+  std::vector<unsigned char> last_qp_args;   // kernel arguments of the last damage solve's passes
+  int32_t last_qp_cheb = 0;                  // its polynomial degree (0: Jacobi)
   pf::Ctl* ctl_pinned = nullptr;     // pinned host copy of the control blocks
   hipEvent_t poll_ev = nullptr;      // marks the copy of the control blocks (convergence polls)
   bool timing = false;

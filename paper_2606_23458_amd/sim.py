@@ -497,6 +497,10 @@ class Simulator:
                         "resid": float(resid)})
         return out
 
+    def repeat_damage_pass(self, n: int) -> None:
+        """n back-to-back launches of the damage pass the last solve stopped at (pf_damage_pass_repeat)."""
+        L.call("pf_damage_pass_repeat", self.mesh.handle, int(n), _stream())
+
     def timer(self, on: bool) -> None:
         L.call("pf_timer_enable", self.mesh.handle, 1 if on else 0)
 
