@@ -37,6 +37,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* 
   }
 }
 
+// Visit the corners of owned node g in its list order.  The corner ids are
+// read from memory kCornerBatch at a time, every load of a batch issued before
+// the first is used (indices past the list end are clamped to its last entry
+// and skipped), so a node's list costs one memory round trip, not one per
+// corner.
+constexpr int kCornerBatch = 8;
+template <typename F>
+__device__ __forceinline__ void for_corners(const DevMesh& dm, int g, F&& f) {
+  const int j0 = dm.lrow[g], j1 = dm.lrow[g + 1];
+  for (int j = j0; j < j1; j += kCornerBatch) {
+    int cc[kCornerBatch];
+#pragma unroll
+    for (int u = 0; u < kCornerBatch; ++u) cc[u] = dm.lcorner[min(j + u, j1 - 1)];
+#pragma unroll
+    for (int u = 0; u < kCornerBatch; ++u)
+      if (j + u < j1) f(cc[u]);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T>* __restrict__ ip, double* part, const T* __restrict__ lam,
                                                        const T* __restrict__ dnp1, const T* __restrict__ Hnp1,
@@ -101,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
   for (int i = tid; i < t.n_own; i += kBlock) {
     const int g = t.node_begin + i;
     T qi = T(0);
-    for (int j = dm.lrow[g]; j < dm.lrow[g + 1]; ++j) qi += qc[dm.lcorner[j]];
+    for_corners(dm, g, [&](int cc) { qi += qc[cc]; });
     dprev_bar[g] = (W[g] == 1) ? dbar[g] - qi : T(0);
   }
   gsum = block_sum(gsum, red);
@@ -194,12 +213,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
   for (int i = tid; i < t.n_own; i += kBlock) {
     const int g = t.node_begin + i;
     T ux = adj1.ux[g], uy = adj1.uy[g], dd = T(0);
-    for (int j = dm.lrow[g]; j < dm.lrow[g + 1]; ++j) {
-      const int cc = dm.lcorner[j];
+    for_corners(dm, g, [&](int cc) {
       ux += cux[cc];
       uy += cuy[cc];
       dd += cdd[cc];
-    }
+    });
     const T vbx = adj1.vx[g], vby = adj1.vy[g];
     adj0.ux[g] = ux;
     adj0.uy[g] = uy;
