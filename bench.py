@@ -387,8 +387,9 @@ def damage_pass_b2b(res, passes: int = 100, reps: int = 3) -> float | None:
     for _ in range(5):
         sim.explicit(sim.state, sim._next)
         sim.damage(sim._next.H, sim.state.d, sim._next.d, sim._active_next, sim.active, cg=cg)
+        arrays = (sim._next.H, sim.state.d, sim._next.d)
         try:
-            sim.repeat_damage_pass(10)   # warm-up; refused unless the solve stopped in a CG iteration
+            sim.repeat_damage_pass(10, *arrays)   # warm-up; refused unless the solve stopped in a CG iteration
             break
         except L.PfError:
             sim.step()
@@ -399,7 +400,7 @@ def damage_pass_b2b(res, passes: int = 100, reps: int = 3) -> float | None:
     for _ in range(reps):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
-        sim.repeat_damage_pass(passes)
+        sim.repeat_damage_pass(passes, *arrays)
         ev1.record()
         gpu_sync()
         ts.append(ev0.elapsed_time(ev1) / passes / 1e3)

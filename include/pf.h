@@ -404,17 +404,19 @@ pf_status_t pf_timer_read(pf_mesh_t m, int32_t family, double* total_ms, int64_t
  * Throughput of the damage CG pass (a measurement aid, outside the solver):
  * enqueues n_passes >= 1 launches of the pass that the handle's last
  * pf_damage_solve call would run next, back to back on `stream`, with no
- * reduction in between.  The last call must have stopped mid-solve in a
- * conjugate-gradient iteration (check_every = 0 and a round budget the solve
- * did not reach) with the Jacobi preconditioner, on arrays that are still
- * allocated; otherwise PF_ERR_ARG (the test reads the control blocks back, a
- * synchronisation of `stream`).  Each launch reads the same current vectors
- * and writes the same next ones, so every launch moves the bytes of one
- * iterate pass; the search direction is updated in place each time, so the
- * solve cannot be continued (resume) afterwards and the caller's damage array
+ * reduction in between.  H, d_prev and d are the device arrays that call
+ * was given (same layout and ownership; the pass reads d_prev, the bounds).
+ * The last call must have stopped mid-solve in a conjugate-gradient
+ * iteration (check_every = 0 and a round budget the solve did not reach)
+ * with the Jacobi preconditioner; otherwise PF_ERR_ARG (the test reads the
+ * control blocks back, a synchronisation of `stream`).  Each launch reads the
+ * same current vectors and writes the same next ones, so every launch moves
+ * the bytes of one iterate pass; the search direction is updated in place
+ * each time, so the solve cannot be continued (resume) afterwards, and d
  * keeps the iterate the last call left.
  */
-pf_status_t pf_damage_pass_repeat(pf_mesh_t m, int32_t n_passes, pf_stream_t stream);
+pf_status_t pf_damage_pass_repeat(pf_mesh_t m, const void* H, const void* d_prev, void* d, int32_t n_passes,
+                                  pf_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -111,7 +111,7 @@ PROTOTYPES = {
     "pf_subcycle_limit": [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
     "pf_timer_enable": [C.c_void_p, C.c_int32],
     "pf_timer_read": [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
-    "pf_damage_pass_repeat": [C.c_void_p, C.c_int32, C.c_void_p],
+    "pf_damage_pass_repeat": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
 }
 
 

@@ -938,11 +938,16 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
 // n launches of the main pass of the last damage solve's current round, with
 // no reduction in between (a throughput measurement; see pf.h).
 template <typename T>
-static pf_status_t repeat_pass(pf_mesh_s* m, int n, hipStream_t s) {
+static pf_status_t repeat_pass(pf_mesh_s* m, const void* H, const void* d_prev, void* d, int n, hipStream_t s) {
   DmgArgs<T> a;
   if (m->last_qp_args.size() != sizeof(a)) return fail(PF_ERR_ARG, "no damage solve on this handle");
   if (m->last_qp_cheb != 0) return fail(PF_ERR_ARG, "repeated passes need the Jacobi preconditioner");
   std::memcpy(&a, m->last_qp_args.data(), sizeof(a));
+  // the caller's arrays as given now; the workspaces are the handle's
+  a.H = static_cast<const T*>(H);
+  a.lb = static_cast<const T*>(d_prev);
+  a.dout = static_cast<T*>(d);
+  a.guess = nullptr;
   PF_HIP(hipMemcpyAsync(m->ctl_pinned, m->dw.ctl, sizeof(Ctl) * m->n_inst, hipMemcpyDeviceToHost, s));
   PF_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < m->n_inst; ++k)
@@ -986,9 +991,12 @@ extern "C" pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const 
   return damage_cg(m, CG_QP, H, d_prev, d, active_guess, active_out, opts, stats, s);
 }
 
-extern "C" pf_status_t pf_damage_pass_repeat(pf_mesh_t m, int32_t n_passes, pf_stream_t stream) {
+extern "C" pf_status_t pf_damage_pass_repeat(pf_mesh_t m, const void* H, const void* d_prev, void* d,
+                                             int32_t n_passes, pf_stream_t stream) {
   if (!m) return fail(PF_ERR_ARG, "mesh is NULL");
+  if (!H || !d_prev || !d) return fail(PF_ERR_ARG, "NULL argument");
   if (n_passes < 1) return fail(PF_ERR_ARG, "n_passes must be >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return (m->dtype == PF_F64) ? repeat_pass<double>(m, n_passes, s) : repeat_pass<float>(m, n_passes, s);
+  return (m->dtype == PF_F64) ? repeat_pass<double>(m, H, d_prev, d, n_passes, s)
+                              : repeat_pass<float>(m, H, d_prev, d, n_passes, s);
 }

@@ -497,9 +497,11 @@ class Simulator:
                         "resid": float(resid)})
         return out
 
-    def repeat_damage_pass(self, n: int) -> None:
-        """n back-to-back launches of the damage pass the last solve stopped at (pf_damage_pass_repeat)."""
-        L.call("pf_damage_pass_repeat", self.mesh.handle, int(n), _stream())
+    def repeat_damage_pass(self, n: int, H: torch.Tensor, d_prev: torch.Tensor, d: torch.Tensor) -> None:
+        """n back-to-back launches of the damage pass the last solve stopped at (pf_damage_pass_repeat);
+        H, d_prev and d are the arrays that solve was given."""
+        L.call("pf_damage_pass_repeat", self.mesh.handle, H.data_ptr(), d_prev.data_ptr(), d.data_ptr(), int(n),
+               _stream())
 
     def timer(self, on: bool) -> None:
         L.call("pf_timer_enable", self.mesh.handle, 1 if on else 0)

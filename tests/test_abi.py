@@ -111,7 +111,7 @@ def test_argument_errors():
     assert lib.pf_subcycle_limit(None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_energies(None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_set_gc_field(None, None, None, None) == L.PF_ERR_ARG
-    assert lib.pf_damage_pass_repeat(None, 1, None) == L.PF_ERR_ARG
+    assert lib.pf_damage_pass_repeat(None, None, None, None, 1, None) == L.PF_ERR_ARG
     res = L.TuneResult()
     descs = (L.MeshDesc * 1)()
     params = (L.Params * 1)()

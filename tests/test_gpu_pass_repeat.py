@@ -29,16 +29,17 @@ def test_repeat_keeps_the_damage_array_and_needs_a_cg_iteration():
     st = sim.cg_stats()[0]
     assert st["flags"] & L.PF_FLAG_NOT_CONVERGED, st
     d0 = s_out.d.clone()
-    sim.repeat_damage_pass(5)
+    arrays = (s_out.H, sim.state.d, s_out.d)
+    sim.repeat_damage_pass(5, *arrays)
     torch.cuda.synchronize()
     assert torch.equal(s_out.d, d0)
     # a solve that finished is refused
     sim.damage(s_out.H, sim.state.d, s_out.d, sim._active_next, sim.active)
     torch.cuda.synchronize()
     with pytest.raises(L.PfError, match="CG iteration"):
-        sim.repeat_damage_pass(1)
+        sim.repeat_damage_pass(1, *arrays)
     with pytest.raises(L.PfError, match="n_passes"):
-        sim.repeat_damage_pass(0)
+        sim.repeat_damage_pass(0, *arrays)
 
 
 def test_repeat_refuses_the_polynomial_preconditioner():
@@ -51,4 +52,4 @@ def test_repeat_refuses_the_polynomial_preconditioner():
     sim.damage(sim._next.H, sim.state.d, sim._next.d, sim._active_next, sim.active, cg=cg)
     torch.cuda.synchronize()
     with pytest.raises(L.PfError, match="Jacobi"):
-        sim.repeat_damage_pass(1)
+        sim.repeat_damage_pass(1, sim._next.H, sim.state.d, sim._next.d)
