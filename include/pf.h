@@ -408,8 +408,10 @@ pf_status_t pf_timer_read(pf_mesh_t m, int32_t family, double* total_ms, int64_t
  * was given (same layout and ownership; the pass reads d_prev, the bounds).
  * The last call must have stopped mid-solve in a conjugate-gradient
  * iteration (check_every = 0 and a round budget the solve did not reach)
- * with the Jacobi preconditioner; otherwise PF_ERR_ARG (the test reads the
- * control blocks back, a synchronisation of `stream`).  Each launch reads the
+ * with the Jacobi preconditioner, and no pf_step_backward call may have run
+ * on the handle since (its adjoint solve reuses the control blocks);
+ * otherwise PF_ERR_ARG where the control blocks show it (the test reads them
+ * back, a synchronisation of `stream`).  Each launch reads the
  * same current vectors and writes the same next ones, so every launch moves
  * the bytes of one iterate pass; the search direction is updated in place
  * each time, so the solve cannot be continued (resume) afterwards, and d
