@@ -19,8 +19,11 @@ def mesh_of(nx, ny, h, jitter=0.0, seed=0, random_diag=False):
 
 
 def quadrature_system(mesh, H, Gc, l0, model):
-    """Dense A and b from a degree-2 exact edge-midpoint rule on every element."""
+    """Dense A and b from a degree-2 exact edge-midpoint rule on every element.
+
+    Gc is a scalar or one value per element."""
     n = mesh.n_nodes
+    Gce = np.broadcast_to(np.asarray(Gc, dtype=np.float64), (len(mesh.tri),))
     A = np.zeros((n, n))
     b = np.zeros(n)
     X = mesh.xy.numpy()
@@ -31,10 +34,11 @@ def quadrature_system(mesh, H, Gc, l0, model):
         C = np.linalg.inv(P)
         grads = C[1:, :].T                       # row k = grad phi_k
         area = abs(np.linalg.det(P)) / 2
+        g = Gce[e]
         if model == 2:
-            kappa, c, load = Gc * l0, Gc / l0 + 2 * H[e], 2 * H[e]
+            kappa, c, load = g * l0, g / l0 + 2 * H[e], 2 * H[e]
         else:
-            kappa, c, load = 0.75 * Gc * l0, 2 * H[e], 2 * H[e] - 3 * Gc / (8 * l0)
+            kappa, c, load = 0.75 * g * l0, 2 * H[e], 2 * H[e] - 3 * g / (8 * l0)
         Ke = area * grads @ grads.T
         Me = sum(area / 3 * np.outer(p, p) for p in pts)
         fe = sum(area / 3 * p for p in pts)
