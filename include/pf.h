@@ -110,9 +110,13 @@ typedef struct {
     int32_t bounds;          /* PF_BOUNDS_PROJECTED | PF_BOUNDS_POSTCLAMP (AT2 only) */
 } pf_params_t;
 
-/* Device pointers to one state; node arrays [n_nodes_total], H [n_elems_total]. */
+/* Device pointers to one state; node arrays [n_nodes_total], H [n_elems_total].
+ * t is the time of the state, device double [n_instances] (the loading
+ * ramps of pf_set_loading are functions of it); NULL where the caller keeps
+ * no time (allowed unless loading is registered; adjoint states ignore it). */
 typedef struct {
     void *ux, *uy, *vx, *vy, *ax, *ay, *d, *H;
+    double* t;
 } pf_state_t;
 
 typedef struct {
@@ -227,9 +231,14 @@ pf_status_t pf_mesh_elem_perm(pf_mesh_t m, int32_t* out);
  *   H_{n+1} = psi+(eps_e) if psi+ > H_n else H_n  (one value per element)
  * `p` and `dt` are host arrays with one entry per instance.  Reads in->{u,v,a,d,H};
  * writes out->{u,v,a,H}; out->d is not touched.  `in` and `out` must not share
- * any array.  f_ext is a device array [2][n_nodes_total] (x block, then y
+ * any array.  When in->t and out->t are both given, out->t = in->t + dt (in
+ * FP64).  f_ext is a device array [2][n_nodes_total] (x block, then y
  * block) or NULL for no external force.  Prescribed DOFs keep their
- * velocity (a must be 0 there in `in`).
+ * velocity (a must be 0 there in `in`), unless pf_set_loading registered
+ * ramped loads: then in->t and out->t are required, f_ext must be NULL, the
+ * external force is S(t_{n+1}) F and prescribed DOFs move with the ramped
+ * velocity (see pf_set_loading), all evaluated inside the kernel from in->t,
+ * so the step stays capturable in a HIP graph.
  */
 pf_status_t pf_explicit_step(pf_mesh_t m, const pf_params_t* p, const double* dt,
                              const pf_state_t* in, pf_state_t* out, const void* f_ext,
@@ -316,6 +325,34 @@ pf_status_t pf_energies(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, 
  * updated (capture them again).
  */
 pf_status_t pf_set_gc_field(pf_mesh_t m, const void* phi, double* dgc_field, pf_stream_t stream);
+
+/*
+ * Ramped boundary loads of the explicit step (the loading protocols of
+ * Sec. 3: eq. smooth_traction_ramp, eq. kalthoff_velocity_ramp).  With
+ * t_n = in->t[k] and t_{n+1} = t_n + dt of instance k, every later
+ * pf_explicit_step uses
+ *   f_ext = S_k(t_{n+1}) F,  S(t) = 0 for t <= 0, (1 - cos(pi t / t_r))/2 for
+ *           0 < t < t_r, 1 for t >= t_r  (t_r = t_traction[k]; t_r <= 0
+ *           gives S = 1 for t > 0);
+ *   v     = R_k(t_n + dt/2) v_full on the prescribed DOFs, R(t) = min(max(t, 0), t_v)/t_v
+ *           (t_v = t_velocity[k]; t_v <= 0 gives R = 1); evaluated at the step
+ *           midpoint, so u += dt v moves a prescribed DOF by the exact integral
+ *           of the linear ramp over the step.  The velocity the step writes
+ *           to out->v there is that value.
+ *   F:       device [2][n_nodes_total] (x block, then y block) full-load
+ *            nodal force, mesh dtype, or NULL for no traction.
+ *   v_full:  device [2][n_nodes_total] velocity of the prescribed DOFs at
+ *            full ramp (other entries are not read), mesh dtype, or NULL to
+ *            keep the state's velocity on prescribed DOFs.
+ *   t_traction, t_velocity: host double [n_instances], finite; NULL = zeros.
+ * F and v_full are copied into the handle (the caller may free them on
+ * return); the first call allocates 4 node vectors there.  F = v_full = NULL
+ * clears the loading.  pf_step_backward then treats the prescribed
+ * velocities as inputs of no adjoint.  A set-up call: it synchronises
+ * `stream`; HIP graphs captured before it are not updated.
+ */
+pf_status_t pf_set_loading(pf_mesh_t m, const void* F, const void* v_full, const double* t_traction,
+                           const double* t_velocity, pf_stream_t stream);
 
 /*
  * CFL time step of every instance (Sec. 2.3): dt_k = factor * h_min,k / c_p,k

@@ -20,7 +20,11 @@ mode.
 
 The exact minimiser is found by a primal-dual active-set iteration with a
 sparse LU solve on the free set; the result is verified against the KKT
-conditions.  Reading: the damage operator uses g = (1-d)^2 without eta.
+conditions.  For the full-size plates the free-set systems can instead be
+solved by SciPy's conjugate gradients (Jacobi-preconditioned, relative
+residual 1e-14): the same active-set iteration and KKT check, an order of
+magnitude faster at a million unknowns.  Reading: the damage operator uses
+g = (1-d)^2 without eta.
 """
 from __future__ import annotations
 
@@ -125,14 +129,29 @@ def kkt_residuals(A, b, lb, x, ub=None):
     return viol, rf, ra, ru
 
 
+def solve_spd(A, rhs, inner: str = "lu") -> np.ndarray:
+    """Solve A x = rhs for a sparse SPD matrix: sparse LU ('lu') or Jacobi-preconditioned
+    conjugate gradients to a relative residual of 1e-14 ('cg')."""
+    if inner == "lu":
+        return spla.spsolve(sp.csc_matrix(A), rhs)
+    if inner != "cg":
+        raise ValueError(inner)
+    if not np.any(rhs):
+        return np.zeros(len(rhs))
+    x, info = spla.cg(A, rhs, rtol=1e-14, atol=0.0, M=sp.diags(1.0 / A.diagonal()), maxiter=50000)
+    if info != 0:
+        raise RuntimeError(f"conjugate gradients did not converge (info={info})")
+    return x
+
+
 def solve_box_qp(A, b, lb, ub=None, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9,
-                 kkt_tol: float = 1e-13):
+                 kkt_tol: float = 1e-13, inner: str = "lu"):
     """Exact minimiser of 1/2 x'Ax - b'x subject to lb <= x <= ub (ub = None: no upper bound).
 
     Primal-dual active set on the gradient g = A x - b: a node is held at its
     lower bound when g_i + A_ii (lb_i - x_i) > 0 and at its upper bound when
     g_i + A_ii (ub_i - x_i) < 0; free nodes solve A_FF x_F = b_F - A_FH x_H
-    exactly (sparse LU).  The iteration stops as soon as the iterate satisfies
+    exactly (solve_spd).  The iteration stops as soon as the iterate satisfies
     the KKT conditions to rounding (free nodes inside the bounds to kkt_tol,
     scaled multipliers of held nodes of the right sign to kkt_tol), or when
     the sets repeat.  Nodes at a degenerate free boundary (x_i at a bound with
@@ -159,7 +178,7 @@ def solve_box_qp(A, b, lb, ub=None, x0=None, max_iter: int = 200, check: bool = 
         if free.any():
             Aff = A[free][:, free].tocsc()
             rhs = b[free] - A[free][:, held] @ x[held]
-            x[free] = spla.spsolve(Aff, rhs) if free.sum() > 1 else rhs / Aff.toarray()[0, 0]
+            x[free] = solve_spd(Aff, rhs, inner) if free.sum() > 1 else rhs / Aff.toarray()[0, 0]
         g = A @ x - b
         g[free] = 0.0
         if (np.all(x[free] >= lb[free] - kkt_tol) and np.all(x[free] <= ub[free] + kkt_tol)
@@ -181,9 +200,10 @@ def solve_box_qp(A, b, lb, ub=None, x0=None, max_iter: int = 200, check: bool = 
 
 
 def solve_bound_qp(A, b, lb, x0=None, max_iter: int = 200, check: bool = True, tol: float = 1e-9,
-                   kkt_tol: float = 1e-13):
+                   kkt_tol: float = 1e-13, inner: str = "lu"):
     """Exact minimiser of 1/2 x'Ax - b'x subject to x >= lb; returns (x, active mask)."""
-    x, lo, _ = solve_box_qp(A, b, lb, None, x0=x0, max_iter=max_iter, check=check, tol=tol, kkt_tol=kkt_tol)
+    x, lo, _ = solve_box_qp(A, b, lb, None, x0=x0, max_iter=max_iter, check=check, tol=tol, kkt_tol=kkt_tol,
+                            inner=inner)
     return x, lo
 
 
@@ -194,6 +214,7 @@ class DamageQP:
     l0: float
     model: int
     bounds: str = "projected"
+    inner: str = "lu"          # free-set solver of the active-set iteration (solve_spd)
 
     def __post_init__(self):
         self.K = stiffness_matrix(self.mesh)
@@ -212,7 +233,7 @@ class DamageQP:
         """
         A, b = self.system(H, Gc, phi)
         if self.bounds == "projected":
-            x, lo, up = solve_box_qp(A, b, d_prev, np.ones(len(b)), x0=d_prev)
+            x, lo, up = solve_box_qp(A, b, d_prev, np.ones(len(b)), x0=d_prev, inner=self.inner)
             return x, lo, up, x, A
         if self.bounds == "postclamp":
             x = spla.spsolve(A.tocsc(), b)

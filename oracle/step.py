@@ -77,7 +77,8 @@ def initial_state(problem) -> State:
 class Sim:
     """Mesh, material and constant operators of one problem."""
 
-    def __init__(self, problem, dt: float | None = None, material: Material | None = None, gc_scale=None):
+    def __init__(self, problem, dt: float | None = None, material: Material | None = None, gc_scale=None,
+                 qp_inner: str = "lu"):
         self.mat = material or Material.of(problem)
         # per-element factor phi of G_c,e = G_c phi_e (None: uniform); a
         # forward-mode dual tensor carries a direction of phi
@@ -87,7 +88,7 @@ class Sim:
         self.minv = 1.0 / self.mass
         self.dt = dt if dt is not None else cfl_dt(self.mesh, self.mat.E, self.mat.nu, self.mat.rho,
                                                     self.mat.plane, problem.cfl)
-        self.qp = DamageQP(self.mesh, self.mat.l0, self.mat.model, self.mat.bounds)
+        self.qp = DamageQP(self.mesh, self.mat.l0, self.mat.model, self.mat.bounds, qp_inner)
 
     def stress(self, u, d):
         """Element strain energy parts and stress for displacement u and damage d."""

@@ -38,7 +38,7 @@ class Params(C.Structure):
 
 
 class StatePtrs(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("ux", "uy", "vx", "vy", "ax", "ay", "d", "H")]
+    _fields_ = [(n, C.c_void_p) for n in ("ux", "uy", "vx", "vy", "ax", "ay", "d", "H", "t")]
 
 
 class CgOpts(C.Structure):
@@ -108,6 +108,8 @@ PROTOTYPES = {
                       C.POINTER(TuneResult), C.c_void_p],
     "pf_energies": [C.c_void_p, C.POINTER(Params), C.POINTER(StatePtrs), C.c_void_p, C.c_void_p],
     "pf_set_gc_field": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "pf_set_loading": [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                       C.c_void_p],
     "pf_subcycle_limit": [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
     "pf_timer_enable": [C.c_void_p, C.c_int32],
     "pf_timer_read": [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(const Ctl* ctl, const dou
 template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> sn,
                                                          StateIn<T> snp1, StateIn<T> adj1,
-                                                         const T* __restrict__ hbar, StateOut<T> adj0) {
+                                                         const T* __restrict__ hbar, StateOut<T> adj0, int vfix) {
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
@@ -219,10 +219,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
       dd += cdd[cc];
     });
     const T vbx = adj1.vx[g], vby = adj1.vy[g];
+    // prescribed velocities set by the loading ramp do not depend on v_n
+    const uint8_t fl = vfix ? dm.fixed[g] : uint8_t(0);
     adj0.ux[g] = ux;
     adj0.uy[g] = uy;
-    adj0.vx[g] = vbx + P.dt * ux;
-    adj0.vy[g] = vby + P.dt * uy;
+    adj0.vx[g] = (fl & 1) ? T(0) : vbx + P.dt * ux;
+    adj0.vy[g] = (fl & 2) ? T(0) : vby + P.dt * uy;
     adj0.ax[g] = P.half_dt * vbx + P.half_dt2 * ux;
     adj0.ay[g] = P.half_dt * vby + P.half_dt2 * uy;
     adj0.d[g] += dd;
@@ -261,18 +263,19 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   const StateIn<T> sn = state_in<T>(s_n), sn1 = state_in<T>(s_np1), a1 = state_in<T>(adj1);
   const StateOut<T> a0 = state_out<T>(adj0);
   const T* hb = static_cast<const T*>(m->dw.hbar);
+  const int vfix = m->ld.vfull != nullptr;
   switch (split) {
     case SPLIT_NONE:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_NONE>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0);
+      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_NONE>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
       break;
     case SPLIT_SPECTRAL:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_SPECTRAL>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0);
+      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_SPECTRAL>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
       break;
     case SPLIT_VOLDEV:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_VOLDEV>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0);
+      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_VOLDEV>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
       break;
     default:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_STAR>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0);
+      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_STAR>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
   }
   timer_end(m, 3, s);
   PF_HIP(hipGetLastError());

@@ -12,15 +12,38 @@
 // corner-force space in LDS so that more workgroups fit on a CU; a node's
 // corner list is sorted by element, so each chunk adds a contiguous run of
 // it and the sums keep their order.
+//
+// Ramped loads (pf_set_loading) are evaluated per workgroup from the state
+// time t_n: the traction factor S(t_{n+1}) scales the registered nodal force
+// and the velocity factor R(t_n + dt/2) the prescribed velocities.
+#include <cmath>
+
 #include "device_common.hpp"
 #include "split.hpp"
 
 namespace pf {
 
+// Smooth traction ramp of Sec. 3 (eq. smooth_traction_ramp): 0 before t = 0,
+// half a cosine wave up to t_r, then 1.
+__device__ __forceinline__ double ramp_smooth(double t, double t_r) {
+  if (t <= 0.0) return 0.0;
+  if (t_r <= 0.0 || t >= t_r) return 1.0;
+  return 0.5 * (1.0 - cos(M_PI * (t / t_r)));
+}
+
+// Linear velocity ramp of Sec. 3 (eq. kalthoff_velocity_ramp), as a fraction
+// of the full velocity.
+__device__ __forceinline__ double ramp_linear(double t, double t_v) {
+  if (t_v <= 0.0 || t >= t_v) return 1.0;
+  return t > 0.0 ? t / t_v : 0.0;
+}
+
 template <typename T, int S, int NPT, int BS>
 __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> in,
-                                                 StateOut<T> out, const T* __restrict__ fext, int nch) {
-  const TileRec t = dm.tiles[tile_of_block(dm.n_tiles)];
+                                                 StateOut<T> out, const T* __restrict__ fext, int nch, LoadDev ld,
+                                                 const double* __restrict__ tin, double* __restrict__ tout) {
+  const int tile = tile_of_block(dm.n_tiles);
+  const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
@@ -47,6 +70,19 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
 #pragma unroll
   for (int k = 0; k < 7; ++k) pg[k] = geo[size_t(k) * nte + pte];
 
+  // ramped loads: the force factor S(t_{n+1}) and the prescribed velocities
+  // R(t_n + dt/2) v_full (the same values in every thread of the workgroup)
+  T fsc = T(1), vsc = T(1);
+  const T* __restrict__ vfull = nullptr;
+  if (ld.par) {
+    const double tn = tin[t.inst];
+    const LoadP lp = ld.par[t.inst];
+    fext = static_cast<const T*>(ld.F);
+    vfull = static_cast<const T*>(ld.vfull);
+    fsc = T(ramp_smooth(tn + P.dtd, lp.t_f));
+    vsc = T(ramp_linear(tn + 0.5 * P.dtd, lp.t_v));
+  }
+
   // ---- phase 1: predictor (eq. vv_u) -------------------------------------
   // the corrector's inputs (lumped mass, prescribed flags, external force)
   // are loaded here too, so that the last phase waits on no memory
@@ -61,9 +97,14 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
       const int g = t.node_begin + i;
       rmi[r] = invw[g];
       rfl[r] = dm.fixed[g];
-      rex[r] = fext ? fext[g] : T(0);
-      rey[r] = fext ? fext[N + g] : T(0);
-      const T vx = in.vx[g], vy = in.vy[g], ax = in.ax[g], ay = in.ay[g];
+      rex[r] = fext ? fsc * fext[g] : T(0);
+      rey[r] = fext ? fsc * fext[N + g] : T(0);
+      T vx = in.vx[g], vy = in.vy[g];
+      const T ax = in.ax[g], ay = in.ay[g];
+      if (vfull) {
+        if (rfl[r] & 1) vx = vsc * vfull[g];
+        if (rfl[r] & 2) vy = vsc * vfull[N + g];
+      }
       const T usx = in.ux[g] + P.dt * vx + P.half_dt2 * ax;
       const T usy = in.uy[g] + P.dt * vy + P.half_dt2 * ay;
       sux[i] = usx;
@@ -75,8 +116,14 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
     }
   }
   auto halo = [&](int i, int g) {
-    sux[i] = in.ux[g] + P.dt * in.vx[g] + P.half_dt2 * in.ax[g];
-    suy[i] = in.uy[g] + P.dt * in.vy[g] + P.half_dt2 * in.ay[g];
+    T vx = in.vx[g], vy = in.vy[g];
+    if (vfull) {
+      const uint8_t fl = dm.fixed[g];
+      if (fl & 1) vx = vsc * vfull[g];
+      if (fl & 2) vy = vsc * vfull[N + g];
+    }
+    sux[i] = in.ux[g] + P.dt * vx + P.half_dt2 * in.ax[g];
+    suy[i] = in.uy[g] + P.dt * vy + P.half_dt2 * in.ay[g];
     sd[i] = in.d[g];
   };
   if (tid < t.n_halo) halo(t.n_own + tid, hg0);
@@ -172,6 +219,8 @@ __global__ __launch_bounds__(BS) void k_explicit(DevMesh dm, const InstP<T>* __r
       out.ay[g] = ayn;
     }
   }
+  // the state time, advanced once per instance (by its first tile)
+  if (tout && tid == 0 && (tile == 0 || dm.tiles[tile - 1].inst != t.inst)) tout[t.inst] = tin[t.inst] + P.dtd;
 }
 
 // Two element chunks when that lets more workgroups share a CU (LDS-bound
@@ -187,6 +236,9 @@ static int explicit_chunks(const pf_mesh_s* m, int bs) {
 template <typename T, int S>
 static hipError_t launch_explicit_s(pf_mesh_s* m, const pf_state_t* in, pf_state_t* out, const void* fext,
                                     hipStream_t s) {
+  const LoadDev ld = m->ld;
+  const double* tin = in->t;
+  double* tout = (in->t && out->t) ? out->t : nullptr;
   const int nch = explicit_chunks(m, m->explicit_block);
   const size_t lds = nch == 2 ? m->max_lds_explicit2 : m->max_lds_explicit;
   const InstP<T>* ip = static_cast<const InstP<T>*>(m->dw.instp);
@@ -197,22 +249,22 @@ static hipError_t launch_explicit_s(pf_mesh_s* m, const pf_state_t* in, pf_state
   if (m->explicit_block == 512) {
     const int npt = (m->max_own + 511) / 512;
     if (npt <= 1)
-      hipLaunchKernelGGL((k_explicit<T, S, 1, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 1, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
     else if (npt <= 2)
-      hipLaunchKernelGGL((k_explicit<T, S, 2, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 2, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
     else
-      hipLaunchKernelGGL((k_explicit<T, S, 4, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 4, 512>), grid, dim3(512), lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
   } else {
     const int npt = (m->max_own + kBlock - 1) / kBlock;
     const dim3 block(kBlock);
     if (npt <= 1)
-      hipLaunchKernelGGL((k_explicit<T, S, 1, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 1, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
     else if (npt <= 2)
-      hipLaunchKernelGGL((k_explicit<T, S, 2, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 2, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
     else if (npt <= 4)
-      hipLaunchKernelGGL((k_explicit<T, S, 4, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 4, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
     else
-      hipLaunchKernelGGL((k_explicit<T, S, 8, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch);
+      hipLaunchKernelGGL((k_explicit<T, S, 8, kBlock>), grid, block, lds, s, m->dm, ip, si, so, fe, nch, ld, tin, tout);
   }
   return hipGetLastError();
 }
@@ -259,6 +311,11 @@ extern "C" pf_status_t pf_explicit_step(pf_mesh_t m, const pf_params_t* p, const
   if ((st = check_state(in, true, true, "in")) != PF_OK) return st;
   if ((st = check_state(out, false, true, "out")) != PF_OK) return st;
   if (states_share(in, out)) return fail(PF_ERR_ARG, "in and out share an array");
+  if (in->t && in->t == out->t) return fail(PF_ERR_ARG, "in and out share the time array");
+  if (m->ld.par) {
+    if (!in->t || !out->t) return fail(PF_ERR_ARG, "ramped loads are registered: in->t and out->t are required");
+    if (f_ext) return fail(PF_ERR_ARG, "ramped loads are registered: f_ext must be NULL");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   m->dt_cache.assign(dt, dt + m->n_inst);
   if ((st = upload_params(m, p, dt, s)) != PF_OK) return st;
@@ -267,5 +324,66 @@ extern "C" pf_status_t pf_explicit_step(pf_mesh_t m, const pf_params_t* p, const
                                       : launch_explicit<float>(m, p[0].split, in, out, f_ext, s);
   timer_end(m, 0, s);
   if (e != hipSuccess) return hip_fail(e, "k_explicit launch");
+  return PF_OK;
+}
+
+namespace pf {
+
+template <typename T>
+static pf_status_t check_finite(const void* a, size_t n, hipStream_t s, const char* name) {
+  std::vector<T> h(n);
+  PF_HIP(hipMemcpyAsync(h.data(), a, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  PF_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(double(h[i]))) return fail(PF_ERR_ARG, std::string(name) + " has a non-finite entry");
+  return PF_OK;
+}
+
+}  // namespace pf
+
+extern "C" pf_status_t pf_set_loading(pf_mesh_t m, const void* F, const void* v_full, const double* t_traction,
+                                      const double* t_velocity, pf_stream_t stream) {
+  if (!m) return fail(PF_ERR_ARG, "mesh is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!F && !v_full) {
+    m->ld = LoadDev{};
+    return PF_OK;
+  }
+  std::vector<LoadP> lp(size_t(m->n_inst));
+  for (int k = 0; k < m->n_inst; ++k) {
+    lp[size_t(k)].t_f = t_traction ? t_traction[k] : 0.0;
+    lp[size_t(k)].t_v = t_velocity ? t_velocity[k] : 0.0;
+    if (!std::isfinite(lp[size_t(k)].t_f) || !std::isfinite(lp[size_t(k)].t_v))
+      return fail(PF_ERR_ARG, "instance " + std::to_string(k) + ": ramp times must be finite");
+  }
+  const bool f64 = m->dtype == PF_F64;
+  const size_t vec = 2 * size_t(m->n_nodes) * (f64 ? sizeof(double) : sizeof(float));
+  for (const void* a : {F, v_full}) {
+    if (!a) continue;
+    const pf_status_t st = f64 ? check_finite<double>(a, 2 * size_t(m->n_nodes), s, a == F ? "F" : "v_full")
+                               : check_finite<float>(a, 2 * size_t(m->n_nodes), s, a == F ? "F" : "v_full");
+    if (st != PF_OK) return st;
+  }
+  const size_t off_v = (vec + 255) / 256 * 256;
+  const size_t off_p = off_v + off_v;
+  if (!m->load_buf) {
+    void* p = nullptr;
+    const size_t bytes = off_p + sizeof(LoadP) * size_t(m->n_inst);
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(PF_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    m->allocs.push_back(p);   // freed with the handle
+    m->device_bytes += bytes;
+    m->load_buf = p;
+  }
+  char* base = static_cast<char*>(m->load_buf);
+  // nothing enqueued earlier on the stream may still read the previous loads
+  PF_HIP(hipStreamSynchronize(s));
+  if (F) PF_HIP(hipMemcpyAsync(base, F, vec, hipMemcpyDeviceToDevice, s));
+  if (v_full) PF_HIP(hipMemcpyAsync(base + off_v, v_full, vec, hipMemcpyDeviceToDevice, s));
+  PF_HIP(hipMemcpyAsync(base + off_p, lp.data(), sizeof(LoadP) * lp.size(), hipMemcpyHostToDevice, s));
+  PF_HIP(hipStreamSynchronize(s));
+  m->ld.F = F ? base : nullptr;
+  m->ld.vfull = v_full ? base + off_v : nullptr;
+  m->ld.par = reinterpret_cast<const LoadP*>(base + off_p);
   return PF_OK;
 }

@@ -106,6 +106,7 @@ static void fill_instp(const pf_params_t& q, double dt, InstP<T>& o) {
   const double lam = (q.plane == PF_PLANE_STRESS) ? lam_ps : lam_pe;
   std::memset(&o, 0, sizeof(o));
   o.dt = T(dt);
+  o.dtd = dt;
   o.half_dt = T(0.5 * dt);
   o.half_dt2 = T(0.5 * dt * dt);
   o.inv_rho = T(1.0 / q.rho);

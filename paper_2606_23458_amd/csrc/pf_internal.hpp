@@ -52,6 +52,20 @@ struct InstP {
   // (efr = Gc/(2 l0)), efr * (int d + l0sq d'Kd) for AT1 (efr = 3 Gc/(8 l0))
   T efr, l0sq;
   int32_t model, bounds, split, pad;
+  double dtd;              // dt in FP64 (advances the state time)
+};
+
+// Ramped loads registered by pf_set_loading: ramp times of one instance.
+struct LoadP {
+  double t_f;              // traction ramp time (<= 0: S = 1 for t > 0)
+  double t_v;              // velocity ramp time (<= 0: R = 1)
+};
+
+// Device view of the registered loads; par is null when none are registered.
+struct LoadDev {
+  const void* F;           // [2][N] full-load nodal force (mesh dtype) or null
+  const void* vfull;       // [2][N] prescribed velocity at full ramp (mesh dtype) or null
+  const LoadP* par;        // [n_inst]
 };
 
 // CG control block of one instance, in device memory.  Fields are read by
@@ -158,6 +172,8 @@ struct pf_mesh_s {
   pf::Timer timers[5];
   void* gcs_buf = nullptr;           // device storage of dm.gcs (allocated by the first pf_set_gc_field)
   double* dgc_field = nullptr;       // caller's per-element dL/dGc_e accumulator, or null
+  void* load_buf = nullptr;          // device storage of the loads (allocated by the first pf_set_loading)
+  pf::LoadDev ld{};                  // the registered loads (ld.par null: none)
 };
 
 namespace pf {

@@ -50,7 +50,7 @@ pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dty
   const size_t per_state = 7 * N * w + Ne * w;
   PF_HIP(hipMalloc(&buf.p, 2 * per_state));
   PF_HIP(hipMemsetAsync(buf.p, 0, 2 * per_state, s));
-  pf_state_t st2[2];
+  pf_state_t st2[2] = {};
   for (int k = 0; k < 2; ++k) {
     char* b = static_cast<char*>(buf.p) + k * per_state;
     void** f[8] = {&st2[k].ux, &st2[k].uy, &st2[k].vx, &st2[k].vy, &st2[k].ax, &st2[k].ay, &st2[k].d, &st2[k].H};

@@ -11,6 +11,7 @@ its conclusions).
 from __future__ import annotations
 
 import ctypes as C
+import time
 
 import numpy as np
 import torch
@@ -61,12 +62,19 @@ class TrajectoryRunner:
                 self.checkpoints.append((sim.state.clone(), sim.active.clone(), sim._next.d.clone()))
         return sim.state
 
-    def backward(self, d_bar: torch.Tensor, field_grad: torch.Tensor | None = None) -> torch.Tensor:
+    def backward(self, d_bar: torch.Tensor, field_grad: torch.Tensor | None = None,
+                 timing: dict | None = None) -> torch.Tensor:
         """Reverse sweep from the adjoint of the final damage; returns dL/dGc per instance (float64).
 
         field_grad (float64 device [n_elems], internal order) also receives
-        dL/dGc_e of every element (the toughness field Gc_e = Gc phi_e)."""
+        dL/dGc_e of every element (the toughness field Gc_e = Gc phi_e).
+        timing, if given, receives the wall seconds spent recomputing segments
+        ('recompute') and in the adjoint steps ('adjoint'); the device is
+        synchronised at every segment boundary for that."""
         mesh = self.sim.mesh
+        self._timing = timing
+        if timing is not None:
+            timing["recompute"] = timing["adjoint"] = 0.0
         if field_grad is None:
             return self._backward(d_bar)
         held = mesh.gc_grad
@@ -75,6 +83,10 @@ class TrajectoryRunner:
             return self._backward(d_bar)
         finally:
             mesh.set_gc_field(mesh.gc_scale, held)
+
+    def _clock(self) -> float:
+        torch.cuda.synchronize()
+        return time.perf_counter()
 
     def _backward(self, d_bar: torch.Tensor) -> torch.Tensor:
         sim = self.sim
@@ -91,9 +103,15 @@ class TrajectoryRunner:
             ck_state, ck_active, ck_dprev = self.checkpoints[sgi]
             states[0].copy_(ck_state)
             self.seg_active[0].copy_(ck_active)
-            self._k0 = k0
+            tm = self._timing
+            t0 = self._clock() if tm is not None else 0.0
             self._recompute(k1 - k0, ck_dprev)
+            t1 = self._clock() if tm is not None else 0.0
             cur, nxt = self._reverse(k1 - k0, cur, nxt, dGc)
+            if tm is not None:
+                t2 = self._clock()
+                tm["recompute"] += t1 - t0
+                tm["adjoint"] += t2 - t1
         self.adj = [cur, nxt]
         return dGc
 
@@ -115,14 +133,14 @@ class TrajectoryRunner:
                              min(budget, sim.cg.max_iter), 0, sim.cg.precond)
         for j in range(n):
             states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
-            sim.explicit(states[j], states[j + 1], sim._loads(self._k0 + j, states[j]))
+            sim.explicit(states[j], states[j + 1])
             sim.damage(states[j + 1].H, states[j].d, states[j + 1].d, act[j + 1], act[j], cg=o,
                        stats=stats[j])
         st = stats[:n].cpu().numpy().reshape(n, -1, 6)
         if np.any(st[:, :, 3] != 0):
             for j in range(n):
                 states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
-                sim.step_into(states[j], states[j + 1], act[j + 1], act[j], sim._loads(self._k0 + j, states[j]))
+                sim.step_into(states[j], states[j + 1], act[j + 1], act[j])
             self._fwd_budget = 0
         else:
             self._fwd_budget = int(st[:, :, 0].max()) + 4

@@ -142,28 +142,33 @@ class Mesh:
 
 
 class State:
-    """Device state: node fields (7, N) = u_x u_y v_x v_y a_x a_y d, and H (Ne)."""
+    """Device state: node fields (7, N) = u_x u_y v_x v_y a_x a_y d, H (Ne) and the
+    time t of every instance (float64; the explicit step advances it)."""
 
-    def __init__(self, mesh: Mesh, nodes: torch.Tensor | None = None, H: torch.Tensor | None = None):
+    def __init__(self, mesh: Mesh, nodes: torch.Tensor | None = None, H: torch.Tensor | None = None,
+                 t: torch.Tensor | None = None):
         self.mesh = mesh
         self.nodes = nodes if nodes is not None else torch.zeros((7, mesh.n_nodes), dtype=mesh.dtype,
                                                                    device=mesh.device)
         self.H = H if H is not None else torch.zeros(mesh.n_elems, dtype=mesh.dtype, device=mesh.device)
+        self.t = t if t is not None else torch.zeros(mesh.n_instances, dtype=torch.float64, device=mesh.device)
 
     def ptrs(self) -> L.StatePtrs:
-        return L.StatePtrs(*[self.nodes[i].data_ptr() for i in range(7)], self.H.data_ptr())
+        return L.StatePtrs(*[self.nodes[i].data_ptr() for i in range(7)], self.H.data_ptr(), self.t.data_ptr())
 
     def clone(self) -> "State":
-        return State(self.mesh, self.nodes.clone(), self.H.clone())
+        return State(self.mesh, self.nodes.clone(), self.H.clone(), self.t.clone())
 
     def copy_(self, other: "State") -> "State":
         self.nodes.copy_(other.nodes)
         self.H.copy_(other.H)
+        self.t.copy_(other.t)
         return self
 
     def zero_(self) -> "State":
         self.nodes.zero_()
         self.H.zero_()
+        self.t.zero_()
         return self
 
     @property
@@ -216,73 +221,36 @@ def default_tol(dtype: str) -> float:
     return 1e-12 if dtype == "f64" else 1e-6
 
 
-def smooth_ramp(t: float, t_r: float) -> float:
-    """Load factor S(t) of the smooth traction ramp (Sec. 3, eq. smooth_traction_ramp)."""
-    if t <= 0.0:
-        return 0.0
-    if t >= t_r:
-        return 1.0
-    return 0.5 * (1.0 - np.cos(np.pi * t / t_r))
-
-
-def velocity_ramp(t: float, t_r: float) -> float:
-    """v(t)/v0 of the velocity ramp (Sec. 3, eq. kalthoff_velocity_ramp)."""
-    if t_r <= 0.0 or t >= t_r:
-        return 1.0
-    return max(t, 0.0) / t_r
-
-
 class Loading:
-    """Ramped boundary loads of a Simulator (Sec. 3 loading protocols).
+    """Ramped boundary loads of a Simulator (Sec. 3 loading protocols), held by the library.
 
     traction: per instance an (N, 2) nodal force reached at full load (or
-    None), applied as f_ext = S(t_{n+1}) F in the explicit step that ends at
-    t_{n+1}; t_traction is the ramp time t_r of S.  t_velocity > 0 ramps the
-    prescribed velocities (the problems' v0 on their fixed DOFs) linearly up
-    to v0 over t_velocity, applied at each step's midpoint t_n + dt/2 (exact
-    displacement increments for the linear ramp).  The values are written into
-    the step's input arrays; every step of the method still runs in the
-    library's kernels.
+    None); the explicit step ending at t_{n+1} applies S(t_{n+1}) F, with S
+    the smooth ramp of time t_traction.  t_velocity > 0 ramps the prescribed
+    velocities (the problems' v0 on their fixed DOFs) linearly up to v0 over
+    t_velocity, evaluated at each step's midpoint.  This class only converts
+    the arrays to the library's node order and registers them
+    (pf_set_loading); the ramps are evaluated in the explicit-step kernel from
+    the state time.
     """
 
     def __init__(self, sim: "Simulator", traction=None, t_traction: float = 0.0, t_velocity: float = 0.0):
         mesh = sim.mesh
-        self.sim = sim
         self.t_traction = float(t_traction)
         self.t_velocity = float(t_velocity)
-        dev = mesh.device
-        # instance of every internal node
-        inst = np.zeros(mesh.n_nodes, dtype=np.int64)
-        for k, inf in enumerate(mesh.info):
-            inst[inf.node_offset:inf.node_offset + inf.n_nodes] = k
-        self.node_inst = torch.tensor(inst, device=dev)
-        self.F = None
+        F = v0 = None
         if traction is not None:
             per = traction if isinstance(traction, (list, tuple)) else [traction]
-            F = mesh.nodes_to_internal([np.asarray(f, dtype=np.float64) for f in per]).T.copy()
-            self.F = torch.tensor(F, dtype=mesh.dtype, device=dev)            # (2, N)
-            self.f_ext = torch.empty_like(self.F)
+            F = torch.tensor(mesh.nodes_to_internal([np.asarray(f, dtype=np.float64) for f in per]).T.copy(),
+                             dtype=mesh.dtype, device=mesh.device)                   # (2, N)
         if self.t_velocity > 0.0:
-            v0 = mesh.nodes_to_internal([np.asarray(p.v0, dtype=np.float64) for p in sim.problems]).T.copy()
-            fx = mesh.nodes_to_internal([np.asarray(p.fixed, dtype=np.float64) for p in sim.problems]).T.copy()
-            self.v0 = torch.tensor(v0, dtype=mesh.dtype, device=dev)
-            self.fixed = torch.tensor(fx > 0.5, device=dev)
-
-    def apply(self, step_index: int, s_in: "State"):
-        """Set the ramped prescribed velocities in s_in; return f_ext for the step (or None)."""
-        sim = self.sim
-        dts = np.asarray(list(sim.dt), dtype=np.float64)
-        if self.t_velocity > 0.0:
-            fac = torch.tensor([velocity_ramp((step_index + 0.5) * dt, self.t_velocity) for dt in dts],
-                               dtype=sim.mesh.dtype, device=sim.mesh.device)[self.node_inst]
-            v = s_in.nodes[2:4]
-            v.copy_(torch.where(self.fixed, self.v0 * fac, v))
-        if self.F is None:
-            return None
-        fac = torch.tensor([smooth_ramp((step_index + 1) * dt, self.t_traction) for dt in dts],
-                           dtype=sim.mesh.dtype, device=sim.mesh.device)[self.node_inst]
-        torch.mul(self.F, fac, out=self.f_ext)
-        return self.f_ext
+            v0 = torch.tensor(mesh.nodes_to_internal([np.asarray(p.v0, dtype=np.float64)
+                                                      for p in sim.problems]).T.copy(),
+                              dtype=mesh.dtype, device=mesh.device)
+        n = mesh.n_instances
+        tf = (C.c_double * n)(*([self.t_traction] * n))
+        tv = (C.c_double * n)(*([self.t_velocity] * n))
+        L.call("pf_set_loading", mesh.handle, _ptr(F), _ptr(v0), tf, tv, _stream())
 
 
 class Simulator:
@@ -340,12 +308,10 @@ class Simulator:
     def set_loading(self, traction=None, t_traction: float = 0.0, t_velocity: float = 0.0) -> None:
         """Ramped loads for the following steps (see Loading); no arguments clears them."""
         if traction is None and t_velocity <= 0.0:
+            L.call("pf_set_loading", self.mesh.handle, None, None, None, None, _stream())
             self.loading = None
         else:
             self.loading = Loading(self, traction, t_traction, t_velocity)
-
-    def _loads(self, step_index: int, s_in: State):
-        return self.loading.apply(step_index, s_in) if self.loading is not None else None
 
     def set_Gc(self, values) -> None:
         for k, v in enumerate(np.atleast_1d(values)):
@@ -414,12 +380,11 @@ class Simulator:
 
     def step(self, n: int = 1) -> State:
         for _ in range(n):
-            f = self._loads(self.steps_done, self.state)
             if self.solves_at(self.steps_done):
-                self.step_into(self.state, self._next, self._active_next, self.active, f)
+                self.step_into(self.state, self._next, self._active_next, self.active)
                 self.active, self._active_next = self._active_next, self.active
             else:
-                self.skip_into(self.state, self._next, f)
+                self.skip_into(self.state, self._next)
             self.state, self._next = self._next, self.state
             self.steps_done += 1
         return self.state
@@ -448,12 +413,11 @@ class Simulator:
                                  min(budget, self.cg.max_iter), 0, self.cg.precond).opts())
             solved = []
             for k in range(w):
-                f = self._loads(self.steps_done + k, self.state)
                 if not self.solves_at(self.steps_done + k):
-                    self.skip_into(self.state, self._next, f)
+                    self.skip_into(self.state, self._next)
                     self.state, self._next = self._next, self.state
                     continue
-                self.explicit(self.state, self._next, f)
+                self.explicit(self.state, self._next)
                 L.call("pf_damage_solve", self.mesh.handle, self.params, self._next.H.data_ptr(),
                        self.state.d.data_ptr(), self._next.d.data_ptr(), self.active.data_ptr(),
                        self._active_next.data_ptr(), o, self._win_stats[k].data_ptr(), _stream())
@@ -526,9 +490,8 @@ class GraphStepper:
     """
 
     def __init__(self, sim: Simulator, rounds: int | None = None, more: int = 4):
-        if sim.n_sub != 1 or sim.loading is not None:
-            raise NotImplementedError("graph replay covers the step with a damage solve (n_sub = 1), "
-                                      "without ramped loads")
+        if sim.n_sub != 1:
+            raise NotImplementedError("graph replay covers the step with a damage solve (n_sub = 1)")
         self.sim = sim
         base = sim.cg
         self.max_iter = base.max_iter

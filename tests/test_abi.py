@@ -35,7 +35,7 @@ def test_struct_layouts_match_header(tmp_path):
         "pf_tile_opts_t": (L.TileOpts, ["tile_nodes", "explicit_block"]),
         "pf_params_t": (L.Params, ["E", "nu", "rho", "Gc", "l0", "eta", "gamma_star", "model", "split", "plane",
                                    "bounds"]),
-        "pf_state_t": (L.StatePtrs, ["ux", "uy", "vx", "vy", "ax", "ay", "d", "H"]),
+        "pf_state_t": (L.StatePtrs, ["ux", "uy", "vx", "vy", "ax", "ay", "d", "H", "t"]),
         "pf_cg_opts_t": (L.CgOpts, ["tol", "max_iter", "check_every", "start", "monotone", "rounds", "resume"]),
         "pf_cg_stats_t": (L.CgStats, ["iters", "restarts", "n_active", "flags", "resid"]),
         "pf_instance_info_t": (L.InstanceInfo, ["node_offset", "n_nodes", "elem_offset", "n_elems", "tile_offset",
@@ -111,6 +111,7 @@ def test_argument_errors():
     assert lib.pf_subcycle_limit(None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_energies(None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_set_gc_field(None, None, None, None) == L.PF_ERR_ARG
+    assert lib.pf_set_loading(None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_damage_pass_repeat(None, None, None, None, 1, None) == L.PF_ERR_ARG
     res = L.TuneResult()
     descs = (L.MeshDesc * 1)()

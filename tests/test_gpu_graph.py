@@ -21,7 +21,7 @@ def _pair(probs, dtype, rounds, more, steps):
         junk = torch.randn(1000, device="cuda").sum()
         torch.cuda.synchronize()
         assert torch.isfinite(junk)
-        for f in ("nodes", "H"):
+        for f in ("nodes", "H", "t"):
             a, b = getattr(eager.state, f), getattr(graph.state, f)
             assert torch.equal(a, b), (k, f)
         assert torch.equal(eager.active, graph.active), k

@@ -99,8 +99,9 @@ def test_qp_unique_kkt_point_by_enumeration(seed):
     assert viol <= 0 and rf < 1e-12 and ra < 1e-12
 
 
+@pytest.mark.parametrize("inner", ["lu", "cg"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_box_qp_unique_kkt_point_by_enumeration(seed):
+def test_box_qp_unique_kkt_point_by_enumeration(seed, inner):
     """P8 (c): with d <= 1 as well, enumerate all 3^9 (free / lower / upper) sets on a 9-node mesh."""
     m, mesh = mesh_of(2, 2, 2.5e-4, 0.2, seed, random_diag=True)
     n = mesh.n_nodes
@@ -126,10 +127,32 @@ def test_box_qp_unique_kkt_point_by_enumeration(seed):
             sols.append(x)
     assert len(sols) >= 1
     assert all(np.allclose(s, sols[0], atol=1e-12, rtol=0) for s in sols)
-    x, lo, up = solve_box_qp(A, b, lb, ub)
+    x, lo, up = solve_box_qp(A, b, lb, ub, inner=inner)
     assert np.max(np.abs(x - sols[0])) < 1e-12
     viol, rf, ra, ru = kkt_residuals(A, b, lb, x, ub)
     assert viol <= 0 and rf < 1e-12 and ra < 1e-12 and ru < 1e-12
+
+
+@pytest.mark.parametrize("model", [1, 2])
+def test_cg_free_set_solver_matches_sparse_lu(model):
+    """The conjugate-gradient free-set solves reach the sparse-LU minimiser of the same box QP
+    (a 96x48 plate with a damaged band and random history), and the dense solve when no bound
+    is active."""
+    m, mesh = mesh_of(96, 48, 2.5e-4, 0.1, 5, random_diag=True)
+    n = mesh.n_nodes
+    r = np.random.default_rng(20 + model)
+    H = r.uniform(0, 6000, mesh.n_elems) * (r.random(mesh.n_elems) < 0.6)
+    lb = np.where(np.abs(m["ij"][:, 1] - 24) <= 2, r.uniform(0.2, 1.0, n), 0.0)
+    A, b = assemble_damage(mesh, H, GC, L0, model)
+    x_lu, lo_lu, up_lu = solve_box_qp(A, b, lb, np.ones(n), x0=lb, inner="lu")
+    x_cg, lo_cg, up_cg = solve_box_qp(A, b, lb, np.ones(n), x0=lb, inner="cg")
+    assert lo_lu.any() and np.max(np.abs(x_cg - x_lu)) < 1e-12
+    viol, rf, ra, ru = kkt_residuals(A, b, lb, x_cg, np.ones(n))
+    assert viol <= 0 and rf < 1e-12 and ra < 1e-12 and ru < 1e-12
+    m2, mesh2 = mesh_of(20, 10, 2.5e-4, 0.1, 6)
+    A2, b2 = assemble_damage(mesh2, r.uniform(100, 5000, mesh2.n_elems), GC, L0, 2)
+    x2, act = solve_bound_qp(A2, b2, np.full(mesh2.n_nodes, -1.0), inner="cg")
+    assert not act.any() and rel(x2, np.linalg.solve(A2.toarray(), b2)) < 1e-12
 
 
 def test_upper_bound_is_a_constraint_of_the_programme():
