@@ -7,9 +7,9 @@
 // dot product and scalar of the CG is accumulated in FP64.
 //
 // Method.  CG runs on the free nodes with the held nodes frozen at a bound
-// (d_prev or 1), and the held set is updated between CG runs (Sec. 2.4:
-// nodes at the lower bound with negative residual are frozen; the solver
-// restarts on the updated free set).  The held set starts from the caller's
+// (d_prev or 1), and the held set is updated between CG runs, the bound
+// treatment of Sec. 2.4 organised as primal-dual active-set steps.  The held
+// set starts from the caller's
 // guess (normally the previous step's flags).  After each converged CG run
 // a check pass recomputes the true residual r = b - Ax, moves free nodes that
 // left [d_prev, 1] onto the bound they crossed, and releases held nodes whose

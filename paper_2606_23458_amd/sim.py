@@ -389,24 +389,42 @@ class Simulator:
             self.steps_done += 1
         return self.state
 
-    def run(self, n: int, window: int = 16, margin: int = 4) -> State:
+    def run(self, n: int, window: int = 16, margin: int = 2) -> State:
         """n staggered steps with the solver's convergence read once per window of steps.
 
         Each step enqueues the explicit step and a fixed budget of CG rounds
         (check_every = 0, so the host never waits inside a step); the budget
-        is the largest round count of the previous window plus `margin`.
-        After a window the per-step statistics are read once: if a solve did
-        not finish within its budget, the window is rolled back to its first
-        state and re-run with step(), which polls.  Rounds after a solve has
-        finished do nothing, so the states equal those of step(n) bit for bit.
+        is the largest round count of the previous window's last eight solves
+        plus `margin` (the first steps of a simulator run polled, to learn
+        it).  After a window the per-step statistics are read once: if a
+        solve did not finish within its budget, the window is rolled back to
+        its first state and re-run with step(), which polls.  Rounds after a
+        solve has finished do nothing, so the states equal those of step(n)
+        bit for bit.
         """
         ni = self.mesh.n_instances
         if getattr(self, "_win_stats", None) is None or self._win_stats.shape[0] < window:
             self._win_stats = torch.zeros((window, ni * 6), dtype=torch.int32, device=self.mesh.device)
-        budget = getattr(self, "_budget", 0) or 32
+        budget = getattr(self, "_budget", 0)
         done = 0
+        if not budget:
+            # no round counts seen yet: the first steps poll
+            k = min(4, n)
+            its = []
+            for _ in range(k):
+                self.step()
+                if self.solves_at(self.steps_done - 1):
+                    its.append(max(s["iters"] for s in self.cg_stats()))
+            budget = (max(its) + margin) if its else 0
+            done = k
         while done < n:
             w = min(window, n - done)
+            if not budget:
+                self.step(w)
+                its = [s["iters"] for s in self.cg_stats()]
+                budget = max(its) + margin if any(self.solves_at(self.steps_done - 1 - j) for j in range(w)) else 0
+                done += w
+                continue
             refs = (self.state, self._next, self.active, self._active_next)
             snap = (self.state.clone(), self._next.d.clone(), self.active.clone())
             o = C.byref(CgConfig(self.cg.tol, self.cg.max_iter, 0, self.cg.start, self.cg.monotone,
@@ -438,7 +456,7 @@ class Simulator:
             else:
                 self.stats.copy_(self._win_stats[solved[-1]])
                 self.steps_done += w
-                budget = int(st[:, :, 0].max()) + margin
+                budget = int(st[-8:, :, 0].max()) + margin
             done += w
         self._budget = budget
         return self.state

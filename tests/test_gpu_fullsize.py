@@ -9,6 +9,8 @@ stress) are too large for the oracle's exact damage QP inside a test, so:
     bound-constrained programme, evaluated in FP64 with the oracle's own
     assembled operator and load vector;
   - batched == plain is checked bitwise on a subset of the 64-plate workload.
+(test_gpu_configs.py hands GPU states of these plates to the oracle and
+compares short windows of staggered steps, damage included.)
 """
 import numpy as np
 import pytest
@@ -46,11 +48,10 @@ def test_full_size_explicit_step(full):
     torch.cuda.synchronize()
     got = s_out.to_user()[0]
     u1, v1, a1, H1, _ = osim.explicit(to_oracle(st))
-    # FP32 kernels against the FP64 oracle
-    assert rel_err(got["u"], u1.numpy()) < 2e-6, name
-    assert rel_err(got["v"], v1.numpy()) < 2e-5, name
-    assert rel_err(got["a"], a1.numpy()) < 2e-3, name
-    assert rel_err(got["H"], H1.numpy()) < 2e-3, name
+    # FP32 kernels against the FP64 oracle: measured at most 2.7e-7 relative on
+    # every field at both sizes; 2e-6 is about 30 units of FP32 rounding
+    for f, ref in (("u", u1), ("v", v1), ("a", a1), ("H", H1)):
+        assert rel_err(got[f], ref.numpy()) < 2e-6, (name, f)
 
 
 def test_full_size_damage_solve_kkt(full):

@@ -3,7 +3,7 @@
 Tolerances: FP64 kernels agree with the oracle to 1e-12 relative on one step
 and 1e-9 relative over a full trajectory; FP32 kernels agree on damage to
 1e-4 (absolute, damage is in [0, 1]) and on the mechanics to a relative error
-set by FP32 rounding (2e-5 over one step).
+set by FP32 rounding (2e-6 over one step, about 30 units of FP32 rounding).
 """
 import numpy as np
 import pytest
@@ -39,11 +39,13 @@ def test_explicit_step_matches_oracle(dtype, split, plane):
     torch.cuda.synchronize()
     got = s_out.to_user()[0]
     u1, v1, a1, H1, _ = osim.explicit(to_oracle(st))
-    tol = 1e-12 if dtype == "f64" else 2e-5
+    # FP32: one step is a few dozen roundings of unit 2^-24 ~ 6e-8 per value;
+    # measured at most 2e-7 relative (a, H), so 2e-6 leaves a factor of ten
+    tol = 1e-12 if dtype == "f64" else 2e-6
     assert rel_err(got["u"], u1.numpy()) < tol
     assert rel_err(got["v"], v1.numpy()) < tol
-    assert rel_err(got["a"], a1.numpy()) < (tol if dtype == "f64" else 1e-3)
-    assert rel_err(got["H"], H1.numpy()) < (tol if dtype == "f64" else 1e-3)
+    assert rel_err(got["a"], a1.numpy()) < tol
+    assert rel_err(got["H"], H1.numpy()) < tol
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
