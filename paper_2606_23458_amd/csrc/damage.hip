@@ -619,26 +619,53 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
 }
 
 // One workgroup per instance: combine the tiles' partials and advance the state.
+// The kernel is latency-bound (one workgroup, a few kilobytes): thread 0 takes
+// the control block into registers and every thread issues the loads of
+// kRedBatch tiles' partials before adding any, so the kernel waits on about
+// one memory round trip instead of one per control-block field and per
+// block-wide stride of tiles.  Each thread still adds its tiles t, t + block,
+// t + 2 block, ... in that order, so the sums do not depend on the batching.
 constexpr int kRedBlock = kBlock;
+constexpr int kRedBatch = 8;
 __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* part, int n_tiles, const int* bounds,
                                                        int kind, double tol, int max_iter) {
   __shared__ double red[8 * 4 * (kRedBlock / 64)];
   __shared__ double tot[8];
-  Ctl* c = ctl + blockIdx.x;
-  const int mode = c->mode;
+  Ctl* const cp = ctl + blockIdx.x;
+  Ctl cc;
+  int bnd = 0;
+  if (threadIdx.x == 0) {
+    cc = *cp;
+    bnd = bounds[blockIdx.x];
+  }
+  const int mode = cp->mode;
   if (mode == MODE_DONE) return;
+  const int tile_end = cp->tile0 + cp->ntiles;
   double v[8] = {0.0, INFINITY, 0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0};
   const size_t nt = size_t(n_tiles);
 #pragma unroll 1
-  for (int k = c->tile0 + threadIdx.x; k < c->tile0 + c->ntiles; k += kRedBlock) {
-    v[PT_DELTA] += part[PT_DELTA * nt + k];
-    v[PT_AMIN] = fmin(v[PT_AMIN], part[PT_AMIN * nt + k]);
-    v[PT_GAMMA] += part[PT_GAMMA * nt + k];
-    v[PT_CF] = fmax(v[PT_CF], part[PT_CF * nt + k]);
-    v[PT_CA] = fmax(v[PT_CA], part[PT_CA * nt + k]);
-    v[PT_NA] += part[PT_NA * nt + k];
-    v[PT_RB] = fmax(v[PT_RB], part[PT_RB * nt + k]);
-    v[PT_CH] += part[PT_CH * nt + k];
+  for (int k0 = cp->tile0 + threadIdx.x; k0 < tile_end; k0 += kRedBatch * kRedBlock) {
+    double q[kRedBatch][8];
+#pragma unroll
+    for (int j = 0; j < kRedBatch; ++j) {
+      const int k = min(k0 + j * kRedBlock, tile_end - 1);   // clamped: loaded, not added
+#pragma unroll
+      for (int f = 0; f < 8; ++f) q[j][f] = part[size_t(f) * nt + k];
+    }
+    // tiles past the end combine as the identity of each operation (selects,
+    // not branches, so the loads above stay ahead of every use)
+#pragma unroll
+    for (int j = 0; j < kRedBatch; ++j) {
+      const bool in = k0 + j * kRedBlock < tile_end;
+      v[PT_DELTA] += in ? q[j][PT_DELTA] : 0.0;
+      v[PT_AMIN] = fmin(v[PT_AMIN], in ? q[j][PT_AMIN] : INFINITY);
+      v[PT_GAMMA] += in ? q[j][PT_GAMMA] : 0.0;
+      v[PT_CF] = fmax(v[PT_CF], in ? q[j][PT_CF] : -INFINITY);
+      v[PT_CA] = fmax(v[PT_CA], in ? q[j][PT_CA] : -INFINITY);
+      v[PT_NA] += in ? q[j][PT_NA] : 0.0;
+      v[PT_RB] = fmax(v[PT_RB], in ? q[j][PT_RB] : -INFINITY);
+      v[PT_CH] += in ? q[j][PT_CH] : 0.0;
+    }
   }
   const double vk = block_reduce_rows<8, kPartOps, kRedBlock / 64>(v, red);
   if (threadIdx.x < 8) tot[threadIdx.x] = vk;
@@ -646,10 +673,11 @@ __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* p
   if (threadIdx.x != 0) return;
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = tot[k];
+  Ctl* const c = &cc;   // the state machine below works on the register copy
   const double sdel = v[PT_DELTA], samin = v[PT_AMIN], sgam = v[PT_GAMMA], scf = v[PT_CF], sca = v[PT_CA];
   const double sna = v[PT_NA], srb = v[PT_RB], sch = v[PT_CH];
   const bool qp = (kind == CG_QP);
-  const bool projected = qp && (bounds[blockIdx.x] == PF_BOUNDS_PROJECTED);
+  const bool projected = qp && (bnd == PF_BOUNDS_PROJECTED);
   const bool monotone = projected && (c->flavor != 0);
   const bool setup = c->setup != 0;
   c->iters += 1;
@@ -750,6 +778,7 @@ __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* p
     c->flags |= PF_FLAG_NOT_CONVERGED;
     c->mode = MODE_DONE;
   }
+  *cp = cc;
 }
 
 // Final pass: bounds, active flags and statistics.
