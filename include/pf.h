@@ -303,6 +303,30 @@ pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt
 pf_status_t pf_energies(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out, pf_stream_t stream);
 
 /*
+ * pf_energies for callers that cannot allocate device memory (code under
+ * HIP-graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels, summation order and results as pf_energies, bit
+ * for bit; the per-tile partial sums live in a fixed array of
+ * 3 * PF_ENERGY_STATIC_MAX_TILES doubles (768 KiB) in device memory that the
+ * library holds on each GPU it runs on until the process ends (its address is
+ * resolved by pf_mesh_create, once per device).  The call allocates nothing,
+ * on the device or through any library.
+ *   - A handle with more than PF_ENERGY_STATIC_MAX_TILES tiles
+ *     (pf_mesh_totals_t.n_tiles) is rejected with PF_ERR_ARG before anything
+ *     is enqueued; use pf_energies for it.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in
+ *     time on one GPU (on different streams, or from several threads) race
+ *     and must be ordered by the caller.  Each call writes every partial it
+ *     reads, so nothing has to be cleared between calls.
+ *   - As in pf_energies, new per-instance parameters are copied to the handle
+ *     with a blocking copy (no allocation); repeated calls with the same
+ *     parameters copy nothing.
+ */
+enum { PF_ENERGY_STATIC_MAX_TILES = 32768 };
+pf_status_t pf_energies_static(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out,
+                               pf_stream_t stream);
+
+/*
  * Spatially varying fracture toughness, Gc_e = Gc * phi_e per element (the
  * per-element Gc(x) inverse problem that Sec. 4 names as the next step; each
  * element's damage weak form, eq. damage_pde_at2 / damage_pde_at1, takes its

@@ -19,6 +19,7 @@ SPLITS = {"none": 0, "spectral": 1, "voldev": 2, "starconvex": 3}
 PLANES = {"strain": 0, "stress": 1}
 BOUNDS = {"projected": 0, "postclamp": 1}
 PF_ACTIVE_LOWER, PF_ACTIVE_UPPER = 1, 2
+PF_ENERGY_STATIC_MAX_TILES = 32768
 PF_FLAG_NOT_CONVERGED, PF_FLAG_NONFINITE = 1, 2
 
 
@@ -107,6 +108,7 @@ PROTOTYPES = {
     "pf_tune_tiles": [C.POINTER(MeshDesc), C.c_int32, C.c_int32, C.POINTER(Params), C.POINTER(TuneOpts),
                       C.POINTER(TuneResult), C.c_void_p],
     "pf_energies": [C.c_void_p, C.POINTER(Params), C.POINTER(StatePtrs), C.c_void_p, C.c_void_p],
+    "pf_energies_static": [C.c_void_p, C.POINTER(Params), C.POINTER(StatePtrs), C.c_void_p, C.c_void_p],
     "pf_set_gc_field": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "pf_set_loading": [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                        C.c_void_p],

@@ -11,6 +11,10 @@
 // One workgroup per tile: owned nodes give the kinetic term, owned elements
 // the elastic and fracture terms (each element once); per-tile FP64 partials
 // are combined per instance in a fixed order by a second launch.
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "device_common.hpp"
 #include "split.hpp"
 
@@ -97,27 +101,57 @@ __global__ __launch_bounds__(kBlock) void k_energy_reduce(const Ctl* ctl, const 
   }
 }
 
+// Partials of pf_energies_static: a fixed array in device memory instead of
+// the handle's workspace (one copy per device, alive until the process
+// ends).  Host code never passes the array's name to a kernel: it uses the
+// device address resolved by energy_scratch_setup.
+static __device__ __align__(256) double scratch[3 * size_t(PF_ENERGY_STATIC_MAX_TILES)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device; null until resolved
+}  // namespace
+
+pf_status_t energy_scratch_setup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return fail(PF_ERR_ARG, "invalid device");
+  if (size_t(device) < g_scratch_ptr.size() && g_scratch_ptr[size_t(device)]) return PF_OK;
+  double* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!ptr) return fail(PF_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+  if (g_scratch_ptr.size() <= size_t(device)) g_scratch_ptr.resize(size_t(device) + 1, nullptr);
+  g_scratch_ptr[size_t(device)] = ptr;
+  return PF_OK;
+}
+
+static double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && size_t(device) < g_scratch_ptr.size()) ? g_scratch_ptr[size_t(device)] : nullptr;
+}
+
 template <typename T>
-static pf_status_t energies_t(pf_mesh_s* m, int split, const pf_state_t* s, double* out, hipStream_t st) {
+static pf_status_t energies_t(pf_mesh_s* m, int split, const pf_state_t* s, double* out, double* part,
+                              hipStream_t st) {
   const dim3 grid(m->n_tiles), block(kBlock);
   const size_t lds = 3 * size_t(m->max_tile_nodes) * sizeof(T) + 64;
   const InstP<T>* ip = static_cast<const InstP<T>*>(m->dw.instp);
   const StateIn<T> si = state_in<T>(s);
   switch (split) {
     case SPLIT_NONE:
-      hipLaunchKernelGGL((k_energy<T, SPLIT_NONE>), grid, block, lds, st, m->dm, ip, si, m->dw.part);
+      hipLaunchKernelGGL((k_energy<T, SPLIT_NONE>), grid, block, lds, st, m->dm, ip, si, part);
       break;
     case SPLIT_SPECTRAL:
-      hipLaunchKernelGGL((k_energy<T, SPLIT_SPECTRAL>), grid, block, lds, st, m->dm, ip, si, m->dw.part);
+      hipLaunchKernelGGL((k_energy<T, SPLIT_SPECTRAL>), grid, block, lds, st, m->dm, ip, si, part);
       break;
     case SPLIT_VOLDEV:
-      hipLaunchKernelGGL((k_energy<T, SPLIT_VOLDEV>), grid, block, lds, st, m->dm, ip, si, m->dw.part);
+      hipLaunchKernelGGL((k_energy<T, SPLIT_VOLDEV>), grid, block, lds, st, m->dm, ip, si, part);
       break;
     default:
-      hipLaunchKernelGGL((k_energy<T, SPLIT_STAR>), grid, block, lds, st, m->dm, ip, si, m->dw.part);
+      hipLaunchKernelGGL((k_energy<T, SPLIT_STAR>), grid, block, lds, st, m->dm, ip, si, part);
       break;
   }
-  hipLaunchKernelGGL(k_energy_reduce, dim3(m->n_inst), block, 0, st, m->dw.ctl, m->dw.part, m->n_tiles, out);
+  hipLaunchKernelGGL(k_energy_reduce, dim3(m->n_inst), block, 0, st, m->dw.ctl, part, m->n_tiles, out);
   PF_HIP(hipGetLastError());
   return PF_OK;
 }
@@ -126,14 +160,33 @@ static pf_status_t energies_t(pf_mesh_s* m, int split, const pf_state_t* s, doub
 
 using namespace pf;
 
-extern "C" pf_status_t pf_energies(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out,
-                                   pf_stream_t stream) {
+static pf_status_t energies_checked(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out,
+                                    pf_stream_t stream, bool fixed_scratch) {
   if (!m || !out) return fail(PF_ERR_ARG, "NULL argument");
   pf_status_t st;
   if ((st = check_params(m, p, nullptr, false)) != PF_OK) return st;
   if ((st = check_state(s, true, false, "state")) != PF_OK) return st;
+  double* part = m->dw.part;
+  if (fixed_scratch) {
+    if (m->n_tiles > PF_ENERGY_STATIC_MAX_TILES)
+      return fail(PF_ERR_ARG, "pf_energies_static: the handle has " + std::to_string(m->n_tiles) +
+                                  " tiles, more than PF_ENERGY_STATIC_MAX_TILES = " +
+                                  std::to_string(PF_ENERGY_STATIC_MAX_TILES) + "; use pf_energies");
+    part = scratch_of(m->device);
+    if (!part) return fail(PF_ERR_HIP, "pf_energies_static: no static partials resolved on this device");
+  }
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if ((st = upload_params(m, p, nullptr, hs)) != PF_OK) return st;
-  return (m->dtype == PF_F64) ? energies_t<double>(m, p[0].split, s, out, hs)
-                              : energies_t<float>(m, p[0].split, s, out, hs);
+  return (m->dtype == PF_F64) ? energies_t<double>(m, p[0].split, s, out, part, hs)
+                              : energies_t<float>(m, p[0].split, s, out, part, hs);
+}
+
+extern "C" pf_status_t pf_energies(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out,
+                                   pf_stream_t stream) {
+  return energies_checked(m, p, s, out, stream, false);
+}
+
+extern "C" pf_status_t pf_energies_static(pf_mesh_t m, const pf_params_t* p, const pf_state_t* s, double* out,
+                                          pf_stream_t stream) {
+  return energies_checked(m, p, s, out, stream, true);
 }

@@ -142,25 +142,38 @@ static void fill_instp(const pf_params_t& q, double dt, InstP<T>& o) {
 }
 
 pf_status_t upload_params(pf_mesh_s* m, const pf_params_t* p, const double* dt, hipStream_t s) {
+  // No allocation here: the host mirror and the bounds array are sized by
+  // pf_mesh_create, and each instance's constants are formed on the stack.
   const size_t sz = (m->dtype == PF_F64) ? sizeof(InstP<double>) : sizeof(InstP<float>);
-  std::vector<unsigned char> buf(sz * m->n_inst);
   if (!dt && !m->dt_cache.empty()) dt = m->dt_cache.data();
+  bool changed = !m->params_valid;
   for (int k = 0; k < m->n_inst; ++k) {
-    double d = dt ? dt[k] : 0.0;
+    const double d = dt ? dt[k] : 0.0;
+    union {
+      InstP<double> f64;
+      InstP<float> f32;
+    } q;
     if (m->dtype == PF_F64)
-      fill_instp<double>(p[k], d, reinterpret_cast<InstP<double>*>(buf.data())[k]);
+      fill_instp<double>(p[k], d, q.f64);
     else
-      fill_instp<float>(p[k], d, reinterpret_cast<InstP<float>*>(buf.data())[k]);
+      fill_instp<float>(p[k], d, q.f32);
+    unsigned char* dst = m->instp_host.data() + sz * size_t(k);
+    if (std::memcmp(dst, &q, sz) != 0) {
+      std::memcpy(dst, &q, sz);
+      changed = true;
+    }
+    if (m->bounds_host[k] != p[k].bounds) {
+      m->bounds_host[k] = p[k].bounds;
+      changed = true;
+    }
   }
-  if (buf != m->instp_host) {
+  if (changed) {
     // Parameters change rarely (a new Gc or dt); a blocking copy keeps the
     // host buffer's lifetime trivial.
-    std::vector<int> bnd(m->n_inst);
-    for (int k = 0; k < m->n_inst; ++k) bnd[k] = p[k].bounds;
     PF_HIP(hipStreamSynchronize(s));
-    PF_HIP(hipMemcpy(m->dw.instp, buf.data(), buf.size(), hipMemcpyHostToDevice));
-    PF_HIP(hipMemcpy(m->dw.bounds, bnd.data(), sizeof(int) * bnd.size(), hipMemcpyHostToDevice));
-    m->instp_host.swap(buf);
+    PF_HIP(hipMemcpy(m->dw.instp, m->instp_host.data(), sz * size_t(m->n_inst), hipMemcpyHostToDevice));
+    PF_HIP(hipMemcpy(m->dw.bounds, m->bounds_host.data(), sizeof(int) * size_t(m->n_inst), hipMemcpyHostToDevice));
+    m->params_valid = true;
   }
   return PF_OK;
 }
@@ -619,6 +632,9 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   if ((st = dev_alloc(m, size_t(n_instances) * psz, &m->dw.instp)) != PF_OK) { free_all(m); delete m; return st; }
   if ((st = dev_alloc(m, size_t(n_instances) * sizeof(int), &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
   m->dw.bounds = static_cast<int*>(tmpp);
+  m->instp_host.assign(size_t(n_instances) * psz, 0);
+  m->bounds_host.assign(size_t(n_instances), -1);
+  m->params_valid = false;
   {
     hipError_t e = hipHostMalloc((void**)&m->ctl_pinned, sizeof(Ctl) * n_instances, hipHostMallocDefault);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipHostMalloc"); }
@@ -668,6 +684,9 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     delete m;
     return fail(PF_ERR_UNSUPPORTED, s);
   }
+  m->device = dev;
+  // device address of the static partials of pf_energies_static on this device
+  if ((st = energy_scratch_setup(dev)) != PF_OK) { free_all(m); delete m; return st; }
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
   if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipStreamSynchronize"); }
   *out = m;

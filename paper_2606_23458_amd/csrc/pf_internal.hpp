@@ -160,7 +160,11 @@ struct pf_mesh_s {
   std::vector<void*> allocs;         // every device allocation, freed at destroy
   size_t device_bytes = 0;
   // host mirror of the current per-instance parameters (bytes of InstP<T>[n_inst])
+  // and of their bounds modes; sized at create, valid once uploaded
   std::vector<unsigned char> instp_host;
+  std::vector<int32_t> bounds_host;
+  bool params_valid = false;
+  int32_t device = 0;                // HIP device the handle was created on
   std::vector<double> dt_cache;      // dt of the last explicit step (the damage solve reuses it)
   int32_t last_rounds[2] = {0, 0};   // CG rounds the last solve of each kind needed (sets the first poll)
   bool qp_started = false;           // a damage solve has been enqueued (resume is allowed)
@@ -208,6 +212,9 @@ enum { CG_QP = 0, CG_LINEAR = 1 };
 pf_status_t damage_cg(pf_mesh_s* m, int kind, const void* H, const void* lb, void* x, const uint8_t* guess,
                       uint8_t* active_out, const pf_cg_opts_t* o, pf_cg_stats_t* stats, hipStream_t s);
 pf_status_t check_state(const pf_state_t* s, bool need_d, bool need_H, const char* name);
+// Resolve, once per device (that device current), the device address of the
+// static partials array of pf_energies_static (energy.hip).
+pf_status_t energy_scratch_setup(int device);
 bool states_share(const pf_state_t* a, const pf_state_t* b);
 
 }  // namespace pf

@@ -461,12 +461,17 @@ class Simulator:
         self._budget = budget
         return self.state
 
-    def energies(self, state: State | None = None) -> list[tuple[float, float, float]]:
-        """(E_kin, E_el, E_frac) of every instance, per unit thickness (pf_energies)."""
+    def energies(self, state: State | None = None, out: torch.Tensor | None = None,
+                 static_scratch: bool = False) -> list[tuple[float, float, float]]:
+        """(E_kin, E_el, E_frac) of every instance, per unit thickness (pf_energies, or with
+        static_scratch pf_energies_static, whose partial sums live in the library's fixed
+        device array; `out`, a device double tensor of 3 n_instances entries, receives them)."""
         st = state or self.state
-        out = torch.empty(self.mesh.n_instances * 3, dtype=torch.float64, device=self.mesh.device)
+        if out is None:
+            out = torch.empty(self.mesh.n_instances * 3, dtype=torch.float64, device=self.mesh.device)
         ptrs = st.ptrs()
-        L.call("pf_energies", self.mesh.handle, self.params, C.byref(ptrs), out.data_ptr(), _stream())
+        L.call("pf_energies_static" if static_scratch else "pf_energies", self.mesh.handle, self.params,
+               C.byref(ptrs), out.data_ptr(), _stream())
         e = out.cpu().numpy().reshape(-1, 3)
         return [tuple(float(x) for x in r) for r in e]
 

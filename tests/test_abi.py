@@ -110,6 +110,7 @@ def test_argument_errors():
     assert lib.pf_tune_tiles(None, 1, 0, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_subcycle_limit(None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_energies(None, None, None, None, None) == L.PF_ERR_ARG
+    assert lib.pf_energies_static(None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_set_gc_field(None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_set_loading(None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_damage_pass_repeat(None, None, None, None, 1, None) == L.PF_ERR_ARG
