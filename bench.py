@@ -1,7 +1,8 @@
 """Benchmark of the explicit phase-field hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32] [--tile-nodes N|auto]
-                    [--no-extras] [--no-cpu] [--cpu-protocol bounded|full] [--copy-calib]
+                    [--no-extras] [--no-cpu] [--cpu-protocol bounded|full] [--sections a,b,...]
+                    [--copy-calib]
 
 Headline: full staggered steps (explicit step + damage solve) of the
 1024x512 plate (1,048,576 triangles, AT2 / vol-dev / plane strain) in FP64,
@@ -644,6 +645,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-protocol", default="bounded", choices=["bounded", "full"])
+    ap.add_argument("--sections", default=None,
+                    help="comma-separated extra sections to run (default: all; names as on the JSON line), "
+                         "e.g. bwd_fwd,batched to profile the backward")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also copy a 256 MiB device buffer 3 times (known traffic, for counter calibration)")
     args = ap.parse_args()
@@ -709,6 +713,9 @@ def main():
                      ("beyond_cache", beyond_cache)]
     if args.dtype == "f32":
         sections = sections[1:]
+    if args.sections is not None:
+        want = [x for x in args.sections.split(",") if x]
+        sections = [(k, fn) for k, fn in sections if k in want]
     for key, fn in sections:
         try:
             out[key] = fn()

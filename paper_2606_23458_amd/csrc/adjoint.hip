@@ -37,24 +37,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* 
   }
 }
 
-// Visit the corners of owned node g in its list order.  The corner ids are
-// read from memory kCornerBatch at a time, every load of a batch issued before
-// the first is used (indices past the list end are clamped to its last entry
-// and skipped), so a node's list costs one memory round trip, not one per
-// corner.
-constexpr int kCornerBatch = 8;
-template <typename F>
-__device__ __forceinline__ void for_corners(const DevMesh& dm, int g, F&& f) {
-  const int j0 = dm.lrow[g], j1 = dm.lrow[g + 1];
-  for (int j = j0; j < j1; j += kCornerBatch) {
-    int cc[kCornerBatch];
-#pragma unroll
-    for (int u = 0; u < kCornerBatch; ++u) cc[u] = dm.lcorner[min(j + u, j1 - 1)];
-#pragma unroll
-    for (int u = 0; u < kCornerBatch; ++u)
-      if (j + u < j1) f(cc[u]);
-  }
-}
+// The owned nodes' corner lists are staged in LDS at kernel entry
+// (stage_corners: offsets and tile-local corner ids 3 e + k, ascending element
+// id), after the kernel's other LDS arrays; each node then adds its corner
+// values in list order from LDS.
+__host__ __device__ __forceinline__ size_t lists_offset(size_t bytes) { return (bytes + 7) & ~size_t(7); }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T>* __restrict__ ip, double* part, const T* __restrict__ lam,
@@ -71,7 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
   T* sl = reinterpret_cast<T*>(smem);
   T* sd = sl + nloc;
   T* qc = sd + nloc;
+  uint16_t* coffs = reinterpret_cast<uint16_t*>(smem + lists_offset((2 * size_t(nloc) + 3 * size_t(t.n_telem)) * sizeof(T)));
+  uint16_t* clist = coffs + t.n_own + 1;
   const int tid = threadIdx.x;
+  stage_corners(dm, t, coffs, clist);
   for (int i = tid; i < nloc; i += kBlock) {
     const int g = (i < t.n_own) ? t.node_begin + i : dm.halo_idx[t.halo_begin + (i - t.n_own)];
     sl[i] = lam[g];
@@ -120,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_damage(DevMesh dm, const InstP<T
   for (int i = tid; i < t.n_own; i += kBlock) {
     const int g = t.node_begin + i;
     T qi = T(0);
-    for_corners(dm, g, [&](int cc) { qi += qc[cc]; });
+    for (int j = coffs[i]; j < coffs[i + 1]; ++j) qi += qc[clist[j]];
     dprev_bar[g] = (W[g] == 1) ? dbar[g] - qi : T(0);
   }
   gsum = block_sum(gsum, red);
@@ -155,7 +145,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
   T* cux = sd + nloc;                    // corner adjoints of u_{n+1}
   T* cuy = cux + 3 * t.n_telem;
   T* cdd = cuy + 3 * t.n_telem;          // corner adjoints of d_n
+  uint16_t* coffs = reinterpret_cast<uint16_t*>(smem + lists_offset((5 * size_t(nloc) + 9 * size_t(t.n_telem)) * sizeof(T)));
+  uint16_t* clist = coffs + t.n_own + 1;
   const int tid = threadIdx.x;
+  stage_corners(dm, t, coffs, clist);
   const T* __restrict__ invw = static_cast<const T*>(dm.inv_w);
   for (int i = tid; i < nloc; i += kBlock) {
     const int g = (i < t.n_own) ? t.node_begin + i : dm.halo_idx[t.halo_begin + (i - t.n_own)];
@@ -213,11 +206,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
   for (int i = tid; i < t.n_own; i += kBlock) {
     const int g = t.node_begin + i;
     T ux = adj1.ux[g], uy = adj1.uy[g], dd = T(0);
-    for_corners(dm, g, [&](int cc) {
+    for (int j = coffs[i]; j < coffs[i + 1]; ++j) {
+      const int cc = clist[j];
       ux += cux[cc];
       uy += cuy[cc];
       dd += cdd[cc];
-    });
+    }
     const T vbx = adj1.vx[g], vby = adj1.vy[g];
     // prescribed velocities set by the loading ramp do not depend on v_n
     const uint8_t fl = vfix ? dm.fixed[g] : uint8_t(0);
@@ -229,6 +223,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
     adj0.ay[g] = P.half_dt * vby + P.half_dt2 * uy;
     adj0.d[g] += dd;
   }
+}
+
+// LDS of an adjoint kernel: nv node values and ne corner values of the mesh
+// dtype per tile (the largest tile of the handle), then the corner lists.
+static size_t adjoint_lds(const pf_mesh_s* m, size_t nv, size_t ne) {
+  size_t vals = 0, lists = 0;
+  for (const TileRec& tr : m->tiles_h) {
+    vals = std::max(vals, (nv * size_t(tr.n_own + tr.n_halo) + ne * size_t(tr.n_telem)) * elem_size(m->dtype));
+    lists = std::max(lists, 2 * (size_t(tr.n_own) + 1 + size_t(tr.n_corner)));
+  }
+  return lists_offset(vals) + lists + 64;
 }
 
 template <typename T>
@@ -247,13 +252,8 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   oa.resume = 0;   // every adjoint solve starts from its own set-up pass
   pf_status_t st = damage_cg(m, CG_LINEAR, s_np1->H, lam, lam, nullptr, nullptr, &oa, stats, s);
   if (st != PF_OK) return st;
-  int32_t max_loc = 0, max_te = 0;
-  for (const TileRec& tr : m->tiles_h) {
-    max_loc = std::max(max_loc, tr.n_own + tr.n_halo);
-    max_te = std::max(max_te, tr.n_telem);
-  }
-  const size_t lds_d = (2 * size_t(max_loc) + 3 * size_t(max_te)) * sizeof(T) + 64;
-  const size_t lds_e = (5 * size_t(max_loc) + 9 * size_t(max_te)) * sizeof(T) + 64;
+  const size_t lds_d = adjoint_lds(m, 2, 3);
+  const size_t lds_e = adjoint_lds(m, 5, 9);
   timer_begin(m, 3, s);
   hipLaunchKernelGGL(k_adj_damage<T>, grid, block, lds_d, s, m->dm, ip, m->dw.part, lam,
                      static_cast<const T*>(s_np1->d), static_cast<const T*>(s_np1->H),
@@ -305,8 +305,7 @@ extern "C" pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const
   if (opts->precond < 0 || opts->precond > 4) return fail(PF_ERR_ARG, "precond must be in [0, 4]");
   if (states_share(adj_n, adj_np1) || states_share(adj_n, s_n) || states_share(adj_n, s_np1))
     return fail(PF_ERR_ARG, "adj_n shares an array with an input");
-  const size_t w = elem_size(m->dtype);
-  const size_t lds_e = (5 * size_t(m->max_tile_nodes) + 9 * size_t(m->max_tile_elems)) * w + 64;
+  const size_t lds_e = adjoint_lds(m, 5, 9);
   int dev = 0, lds_limit = 65536;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds_limit = 65536;
