@@ -923,7 +923,7 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
     // a finished solve costs only two near-empty launches), then every
     // check_every rounds
     const int last = m->last_rounds[kind == CG_QP ? 0 : 1];
-    int chunk = last > 0 ? std::min(last + 2, 64) : std::min(o->check_every, 8);
+    int chunk = last > 0 ? last + 2 : std::min(o->check_every, 8);
     if (o->check_every == 1) chunk = 1;   // poll after every round: no round runs after the solve ends
     while (launched < max_rounds) {
       const int n = std::min(chunk, max_rounds - launched);
@@ -941,7 +941,7 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
       bool all_done = true;
       for (int k = 0; k < m->n_inst; ++k) all_done = all_done && (m->ctl_pinned[k].mode == MODE_DONE);
       if (all_done) break;
-      chunk = std::max(chunk, o->check_every);
+      chunk = o->check_every;
     }
   }
   timer_begin(m, 2, s);
