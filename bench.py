@@ -99,16 +99,17 @@ def events():
 
 
 def plate_simulator(p, tile_nodes, dtype: str):
-    """A Simulator of plate p: tile_nodes 'auto' lets the autotuner pick the whole plan; a
-    number fixes the tile size and the autotuner picks only the explicit-step workgroup shape
-    (so repeated runs and profiles use the same tiles)."""
+    """A Simulator of plate p (or of a list of plates in one handle): tile_nodes 'auto' lets
+    the autotuner pick the whole plan; a number fixes the tile size and the autotuner picks
+    only the explicit-step workgroup shape (so repeated runs and profiles use the same tiles)."""
     from paper_2606_23458_amd import Mesh, Simulator, tune_tiles
+    probs = list(p) if isinstance(p, (list, tuple)) else [p]
     if tile_nodes == "auto":
-        return Simulator(p, dtype=dtype, tile_nodes="auto")
-    rep = tune_tiles([p], dtype, candidates=[int(tile_nodes)])
-    mesh = Mesh([p], dtype, int(tile_nodes), explicit_block=rep["explicit_block"],
+        return Simulator(probs, dtype=dtype, tile_nodes="auto")
+    rep = tune_tiles(probs, dtype, candidates=[int(tile_nodes)])
+    mesh = Mesh(probs, dtype, int(tile_nodes), explicit_block=rep["explicit_block"],
                 explicit_chunks=rep["explicit_chunks"])
-    return Simulator(p, dtype=dtype, mesh=mesh)
+    return Simulator(probs, dtype=dtype, mesh=mesh)
 
 
 def timed_run(sim, steps: int) -> float:
@@ -354,17 +355,18 @@ def perforated(steps: int = 60, warmup: int = 20) -> dict:
 
 def batched_step(steps: int = 30) -> dict:
     """All 64 plates of the inverse workload in one handle (FP32, 6.8M triangles): the explicit
-    step alone (661 MB of algorithmic traffic per step, beyond the 256 MB Infinity Cache) and
+    step alone (612 MB of algorithmic traffic per step, beyond the 256 MB Infinity Cache) and
     full staggered steps."""
     import workloads as w
-    from paper_2606_23458_amd import Simulator
     probs = w.config4(64)
-    sim = Simulator(probs, dtype="f32")
+    sim = plate_simulator(probs, DEFAULT_TILE["f32"], "f32")
     ne = sim.mesh.n_elems
     sim.run(10)
     ms = timed_run(sim, steps)
     ex = explicit_only(sim, steps, 4)
-    return {"workload": f"64 plates 128x64..512x256, {ne} triangles, FP32, one handle", "explicit_step": ex,
+    return {"workload": f"64 plates 128x64..512x256, {ne} triangles, FP32, one handle",
+            "tile_plan": {"tile_nodes": sim.mesh.tile_nodes, "explicit_block": sim.mesh.explicit_block,
+                          "explicit_chunks": sim.mesh.explicit_chunks}, "explicit_step": ex,
             "alg_MB_per_explicit_step": round(alg_bytes_per_elem(0, 4) * ne / 1e6, 1),
             "staggered_ms_per_step": round(ms, 4), "elem_steps_per_s": round(ne / (ms / 1e3), 1)}
 
@@ -543,8 +545,8 @@ def batched_vs_plain(n_inst: int = 64, steps: int = 300, plain: bool = True) -> 
     from paper_2606_23458_amd.grad import TrajectoryRunner
 
     probs = w.config4(n_inst)
-    # batched: one handle, one forward + backward of all instances
-    sim = Simulator(probs, dtype="f32")
+    # batched: one handle, one forward + backward of all instances (explicit-step shape by the autotuner)
+    sim = plate_simulator(probs, DEFAULT_TILE["f32"], "f32")
     runner = TrajectoryRunner(sim, steps=steps, checkpoint_every=50)
     gpu_sync()
     t0 = time.perf_counter()
