@@ -35,7 +35,7 @@
 //     p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
 //     z = M r,  w = A z,  gamma = r'z,  delta = z'w,
 //     beta' = gamma'/gamma,  alpha' = gamma'/(delta' - beta' gamma'/alpha).
-// One round of the solve is two launches over the tile grid:
+// One round of the solve is one or two launches over the tile grid:
 //   k_dmg      one pass of the current phase for every tile of every
 //              instance that is not done:
 //                restart / check: x-matvec in FP64, true residual, held-set
@@ -49,10 +49,14 @@
 //   k_dmg_red  one workgroup per instance combines its tiles' partials in a
 //              fixed order (bitwise reproducible results) and advances the
 //              instance's state.
+// With the Jacobi preconditioner and instances of up to kFuseMaxTiles tiles
+// the combination instead runs at the end of k_dmg, in the instance's last
+// workgroup to finish (arrivals counted by integer atomics; same order, same
+// bits), so such a round is a single launch.
 // r, w, s and x are ping-pong pairs: a pass reads one half and writes the
-// other, so halo reads never race with the owners' writes.  No atomics and no
-// device-wide fences are used.  Linear mode (CG_LINEAR) solves A_FF x_F = b_F
-// for a fixed held set and is used by the adjoint step.
+// other, so halo reads never race with the owners' writes.  No floating-point
+// atomics and no device-wide fences are used.  Linear mode (CG_LINEAR) solves
+// A_FF x_F = b_F for a fixed held set and is used by the adjoint step.
 #include <cstring>
 
 #include "device_common.hpp"
@@ -100,6 +104,11 @@ struct DmgArgs {
   T* dv;               // Chebyshev update direction (owner only)
   int32_t cheb;        // polynomial degree
   int32_t stage;       // pass within a round: 0 main pass, 1 .. cheb-2 Chebyshev steps, cheb-1 the A z pass
+  // combination of the round in the pass's last workgroup (Jacobi rounds):
+  // 0 none (a k_dmg_red launch follows), 1 combine and advance the solver,
+  // 2 combine and run the state machine without storing it (timing aid)
+  int32_t fuse;
+  uint32_t* arrive;    // arrival counters (see kArriveGroup)
 };
 
 // Chebyshev-Jacobi preconditioner z = p(D^-1 A) D^-1 r: `cheb` steps of the
@@ -165,7 +174,7 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
   return v < lo ? lo : (v > T(1) ? T(1) : v);
 }
 
-template <typename T, int NPT, bool CHEB>
+template <typename T, int NPT, bool CHEB, bool FUSE>
 __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[8 * 4 * kWaves];
   const int tile = tile_of_block(a.dm.n_tiles);
@@ -614,66 +623,55 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   double v[8] = {del, amin, gam, cf, ca, na, rb, ch};   // in PT_* order
   const double tot = block_reduce_rows<8, kPartOps>(v, red);
   // partials are stored value-major, [8][n_tiles], so the reduction reads them
-  // coalesced; thread k holds value k
-  if (tid < 8 && (store & (1u << tid))) a.part[size_t(tid) * a.dm.n_tiles + tile] = tot;
+  // coalesced; thread k holds value k.  FUSE (Jacobi rounds): stored through
+  // to the device-coherent level for the combination in this kernel's last
+  // workgroup.
+  if constexpr (FUSE) {
+    if (tid < 8)
+      __hip_atomic_store(&a.part[size_t(tid) * a.dm.n_tiles + tile], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    arrive_and_advance(a, a.ctl + t.inst, tile, P.bounds, red);
+  } else {
+    if (tid < 8 && (store & (1u << tid))) a.part[size_t(tid) * a.dm.n_tiles + tile] = tot;
+  }
 }
 
-// One workgroup per instance: combine the tiles' partials and advance the state.
-// The kernel is latency-bound (one workgroup, a few kilobytes): thread 0 takes
-// the control block into registers and every thread issues the loads of
-// kRedBatch tiles' partials before adding any, so the kernel waits on about
-// one memory round trip instead of one per control-block field and per
-// block-wide stride of tiles.  Each thread still adds its tiles t, t + block,
-// t + 2 block, ... in that order, so the sums do not depend on the batching.
-constexpr int kRedBlock = kBlock;
+// Combination of an instance's per-tile partials, in a fixed order: thread t
+// adds the partials of tiles tile0 + t, tile0 + t + block, ... in that order,
+// then the block's values are reduced (DPP rows, then a fixed-order combine);
+// thread k < 8 returns value k.  k_dmg_red runs the same order with the loads
+// of kRedBatch tiles per thread in flight (it is latency-bound: one
+// workgroup, a few kilobytes; tiles past the end combine as the identity of
+// each operation through selects, not a branch, so the loads stay ahead of
+// every use).  This flavour, for the last workgroup of a pass, reads one
+// tile's partials per thread at a time past this die's L2 (the partials of the
+// running kernel) and keeps the pass's register count.
 constexpr int kRedBatch = 8;
-__global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* part, int n_tiles, const int* bounds,
-                                                       int kind, double tol, int max_iter) {
-  __shared__ double red[8 * 4 * (kRedBlock / 64)];
-  __shared__ double tot[8];
-  Ctl* const cp = ctl + blockIdx.x;
-  Ctl cc;
-  int bnd = 0;
-  if (threadIdx.x == 0) {
-    cc = *cp;
-    bnd = bounds[blockIdx.x];
-  }
-  const int mode = cp->mode;
-  if (mode == MODE_DONE) return;
-  const int tile_end = cp->tile0 + cp->ntiles;
+constexpr int kFuseMaxTiles = 512;   // instances combined in the pass's last workgroup (see run_solve)
+__device__ __forceinline__ double combine_partials(double* part, size_t nt, int tile0, int ntiles, double* red) {
+  const int tile_end = tile0 + ntiles;
   double v[8] = {0.0, INFINITY, 0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0};
-  const size_t nt = size_t(n_tiles);
 #pragma unroll 1
-  for (int k0 = cp->tile0 + threadIdx.x; k0 < tile_end; k0 += kRedBatch * kRedBlock) {
-    double q[kRedBatch][8];
+  for (int k = tile0 + int(threadIdx.x); k < tile_end; k += kBlock) {
+    double q[8];
 #pragma unroll
-    for (int j = 0; j < kRedBatch; ++j) {
-      const int k = min(k0 + j * kRedBlock, tile_end - 1);   // clamped: loaded, not added
-#pragma unroll
-      for (int f = 0; f < 8; ++f) q[j][f] = part[size_t(f) * nt + k];
-    }
-    // tiles past the end combine as the identity of each operation (selects,
-    // not branches, so the loads above stay ahead of every use)
-#pragma unroll
-    for (int j = 0; j < kRedBatch; ++j) {
-      const bool in = k0 + j * kRedBlock < tile_end;
-      v[PT_DELTA] += in ? q[j][PT_DELTA] : 0.0;
-      v[PT_AMIN] = fmin(v[PT_AMIN], in ? q[j][PT_AMIN] : INFINITY);
-      v[PT_GAMMA] += in ? q[j][PT_GAMMA] : 0.0;
-      v[PT_CF] = fmax(v[PT_CF], in ? q[j][PT_CF] : -INFINITY);
-      v[PT_CA] = fmax(v[PT_CA], in ? q[j][PT_CA] : -INFINITY);
-      v[PT_NA] += in ? q[j][PT_NA] : 0.0;
-      v[PT_RB] = fmax(v[PT_RB], in ? q[j][PT_RB] : -INFINITY);
-      v[PT_CH] += in ? q[j][PT_CH] : 0.0;
-    }
+    for (int f = 0; f < 8; ++f) q[f] = __hip_atomic_load(part + size_t(f) * nt + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v[PT_DELTA] += q[PT_DELTA];
+    v[PT_AMIN] = fmin(v[PT_AMIN], q[PT_AMIN]);
+    v[PT_GAMMA] += q[PT_GAMMA];
+    v[PT_CF] = fmax(v[PT_CF], q[PT_CF]);
+    v[PT_CA] = fmax(v[PT_CA], q[PT_CA]);
+    v[PT_NA] += q[PT_NA];
+    v[PT_RB] = fmax(v[PT_RB], q[PT_RB]);
+    v[PT_CH] += q[PT_CH];
   }
-  const double vk = block_reduce_rows<8, kPartOps, kRedBlock / 64>(v, red);
-  if (threadIdx.x < 8) tot[threadIdx.x] = vk;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = tot[k];
-  Ctl* const c = &cc;   // the state machine below works on the register copy
+  return block_reduce_rows<8, kPartOps>(v, red);
+}
+
+// The solver's state machine: one round's combined partials advance the
+// instance's control block c (a register copy; the caller stores it).
+__device__ __forceinline__ void advance_solver(Ctl* c, const double (&v)[8], int bnd, int kind, double tol,
+                                               int max_iter) {
+  const int mode = c->mode;
   const double sdel = v[PT_DELTA], samin = v[PT_AMIN], sgam = v[PT_GAMMA], scf = v[PT_CF], sca = v[PT_CA];
   const double sna = v[PT_NA], srb = v[PT_RB], sch = v[PT_CH];
   const bool qp = (kind == CG_QP);
@@ -778,7 +776,102 @@ __global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* p
     c->flags |= PF_FLAG_NOT_CONVERGED;
     c->mode = MODE_DONE;
   }
+}
+
+// One workgroup per instance: combine the tiles' partials and advance the
+// state (the rounds of the Chebyshev-preconditioned solver, and passes run
+// without the combination in their last workgroup).
+constexpr int kRedBlock = kBlock;
+__global__ __launch_bounds__(kRedBlock) void k_dmg_red(Ctl* ctl, const double* part, int n_tiles, const int* bounds,
+                                                       int kind, double tol, int max_iter) {
+  __shared__ double red[8 * 4 * (kRedBlock / 64)];
+  __shared__ double tot[8];
+  Ctl* const cp = ctl + blockIdx.x;
+  Ctl cc;
+  int bnd = 0;
+  if (threadIdx.x == 0) {
+    cc = *cp;
+    bnd = bounds[blockIdx.x];
+  }
+  if (cp->mode == MODE_DONE) return;
+  const int tile_end = cp->tile0 + cp->ntiles;
+  double v[8] = {0.0, INFINITY, 0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0};
+  const size_t nt = size_t(n_tiles);
+#pragma unroll 1
+  for (int k0 = cp->tile0 + threadIdx.x; k0 < tile_end; k0 += kRedBatch * kRedBlock) {
+    double q[kRedBatch][8];
+#pragma unroll
+    for (int j = 0; j < kRedBatch; ++j) {
+      const int k = min(k0 + j * kRedBlock, tile_end - 1);   // clamped: loaded, not added
+#pragma unroll
+      for (int f = 0; f < 8; ++f) q[j][f] = part[size_t(f) * nt + k];
+    }
+#pragma unroll
+    for (int j = 0; j < kRedBatch; ++j) {
+      const bool in = k0 + j * kRedBlock < tile_end;
+      v[PT_DELTA] += in ? q[j][PT_DELTA] : 0.0;
+      v[PT_AMIN] = fmin(v[PT_AMIN], in ? q[j][PT_AMIN] : INFINITY);
+      v[PT_GAMMA] += in ? q[j][PT_GAMMA] : 0.0;
+      v[PT_CF] = fmax(v[PT_CF], in ? q[j][PT_CF] : -INFINITY);
+      v[PT_CA] = fmax(v[PT_CA], in ? q[j][PT_CA] : -INFINITY);
+      v[PT_NA] += in ? q[j][PT_NA] : 0.0;
+      v[PT_RB] = fmax(v[PT_RB], in ? q[j][PT_RB] : -INFINITY);
+      v[PT_CH] += in ? q[j][PT_CH] : 0.0;
+    }
+  }
+  const double vk = block_reduce_rows<8, kPartOps, kRedBlock / 64>(v, red);
+  if (threadIdx.x < 8) tot[threadIdx.x] = vk;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = tot[k];
+  advance_solver(&cc, v, bnd, kind, tol, max_iter);
   *cp = cc;
+}
+
+// The end of a Jacobi round's pass: each workgroup counts its arrival once its
+// partial sums are stored, and the instance's last workgroup to arrive
+// combines every tile's partials and advances the solver, so a round is one
+// launch.  Nothing waits for anything: a workgroup that is not last exits.
+// The partials are stored through to the device-coherent level (the L2s of
+// the chip's dies are not coherent with each other) and counted only after
+// the stores have completed; the last workgroup reads them past its L2.  The
+// fixed combination order is that of k_dmg_red, so the bits are the same.
+template <typename T>
+__device__ __forceinline__ void arrive_and_advance(const DmgArgs<T>& a, Ctl* c, int tile, int bnd, double* red) {
+  __shared__ int s_last;
+  __shared__ double s_tot[8];
+  const int tid = threadIdx.x;
+  uint32_t* const top = a.arrive + size_t(c->cbase + c->ngroup) * kArriveStride;
+  if (tid < 64) {
+    // threads 0-7 of this wave stored the partials: wait for the stores
+    __builtin_amdgcn_s_waitcnt(0);
+    if (tid == 0) {
+      const int g = (tile - c->tile0) / kArriveGroup;
+      const unsigned gsize = unsigned(min(kArriveGroup, c->ntiles - g * kArriveGroup));
+      uint32_t* const gc = a.arrive + size_t(c->cbase + g) * kArriveStride;
+      bool last = false;
+      if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+        __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               unsigned(c->ngroup) - 1;
+      }
+      s_last = last;
+    }
+  }
+  __syncthreads();
+  if (!s_last) return;
+  const double vk = combine_partials(a.part, size_t(a.dm.n_tiles), c->tile0, c->ntiles, red);
+  if (tid < 8) s_tot[tid] = vk;
+  __syncthreads();
+  if (tid != 0) return;
+  Ctl cc = *c;
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = s_tot[k];
+  advance_solver(&cc, v, bnd, a.kind, a.tol, a.max_iter);
+  if (a.fuse == 1) *c = cc;
+  __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Final pass: bounds, active flags and statistics.
@@ -867,7 +960,17 @@ static DmgArgs<T> dmg_args(pf_mesh_s* m, int kind, const void* H, const void* d_
   a.zb = a.y0 = a.y1 = a.dv = nullptr;
   a.cheb = 0;
   a.stage = 0;
+  a.fuse = 0;
+  a.arrive = m->dw.arrive;
   return a;
+}
+
+// The damage pass for npt owned nodes per thread (a tile of up to 256 npt
+// owned nodes).
+template <typename T, bool CHEB, bool FUSE>
+static void (*dmg_kernel(int npt))(DmgArgs<T>) {
+  return npt <= 1 ? k_dmg<T, 1, CHEB, FUSE>
+                  : (npt <= 2 ? k_dmg<T, 2, CHEB, FUSE> : (npt <= 4 ? k_dmg<T, 4, CHEB, FUSE> : k_dmg<T, 8, CHEB, FUSE>));
 }
 
 template <typename T>
@@ -886,14 +989,18 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
   const int npt = (m->max_own + kBlock - 1) / kBlock;
   const bool cheb = o->precond >= 2;
   a.cheb = cheb ? o->precond : 0;
+  // Jacobi rounds of instances of up to kFuseMaxTiles tiles combine their
+  // partials in the pass's last workgroup (one launch per round: the last
+  // workgroup's combination takes one memory round trip per 256 tiles, which
+  // beats the separate reduction launch only while there are few); larger
+  // instances and Chebyshev rounds keep the reduction launch
+  a.fuse = (!cheb && m->max_inst_tiles <= kFuseMaxTiles) ? 1 : 0;
   a.zb = static_cast<T*>(m->dw.zb);
   a.y0 = static_cast<T*>(m->dw.y0);
   a.y1 = static_cast<T*>(m->dw.y1);
   a.dv = static_cast<T*>(m->dw.dv);
-  auto kdmg = cheb ? (npt <= 1 ? k_dmg<T, 1, true>
-                               : (npt <= 2 ? k_dmg<T, 2, true> : (npt <= 4 ? k_dmg<T, 4, true> : k_dmg<T, 8, true>)))
-                   : (npt <= 1 ? k_dmg<T, 1, false>
-                               : (npt <= 2 ? k_dmg<T, 2, false> : (npt <= 4 ? k_dmg<T, 4, false> : k_dmg<T, 8, false>)));
+  auto kdmg = cheb ? dmg_kernel<T, true, false>(npt)
+                   : (a.fuse ? dmg_kernel<T, false, true>(npt) : dmg_kernel<T, false, false>(npt));
   if (kind == CG_QP) {
     const unsigned char* ab = reinterpret_cast<const unsigned char*>(&a);
     m->last_qp_args.assign(ab, ab + sizeof(a));
@@ -908,6 +1015,7 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
       hipLaunchKernelGGL(kdmg, grid, block, lds, s, as);
       timer_end(m, 1, s);
     }
+    if (a.fuse) return;
     timer_begin(m, 4, s);
     hipLaunchKernelGGL(k_dmg_red, igrid, dim3(kRedBlock), 0, s, m->dw.ctl, m->dw.part, m->n_tiles, m->dw.bounds,
                        kind, o->tol, o->max_iter);
@@ -977,14 +1085,16 @@ static pf_status_t repeat_pass(pf_mesh_s* m, const void* H, const void* d_prev, 
   a.lb = static_cast<const T*>(d_prev);
   a.dout = static_cast<T*>(d);
   a.guess = nullptr;
+  // where the solver's rounds combine the partials in the pass's last
+  // workgroup, each launch does so too but leaves the control block as it is
+  a.fuse = a.fuse ? 2 : 0;
   PF_HIP(hipMemcpyAsync(m->ctl_pinned, m->dw.ctl, sizeof(Ctl) * m->n_inst, hipMemcpyDeviceToHost, s));
   PF_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < m->n_inst; ++k)
     if (m->ctl_pinned[k].mode != MODE_ITER)
       return fail(PF_ERR_ARG, "the last damage solve did not stop in a CG iteration");
   const int npt = (m->max_own + kBlock - 1) / kBlock;
-  auto kdmg = npt <= 1 ? k_dmg<T, 1, false>
-                       : (npt <= 2 ? k_dmg<T, 2, false> : (npt <= 4 ? k_dmg<T, 4, false> : k_dmg<T, 8, false>));
+  auto kdmg = a.fuse ? dmg_kernel<T, false, true>(npt) : dmg_kernel<T, false, false>(npt);
   a.stage = 0;
   for (int i = 0; i < n; ++i)
     hipLaunchKernelGGL(kdmg, dim3(m->n_tiles), dim3(kBlock), m->max_lds_damage, s, a);

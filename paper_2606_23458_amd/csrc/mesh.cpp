@@ -641,16 +641,26 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     e = hipEventCreateWithFlags(&m->poll_ev, hipEventDisableTiming);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipEventCreateWithFlags"); }
   }
-  // tile counts per instance into the control blocks
+  // tile counts per instance into the control blocks, and the arrival counters
   {
     std::vector<Ctl> c(n_instances);
     std::memset(c.data(), 0, sizeof(Ctl) * n_instances);
+    int32_t ncnt = 0;
     for (int k = 0; k < n_instances; ++k) {
       c[k].ntiles = m->info[k].n_tiles;
       c[k].tile0 = m->info[k].tile_offset;
       c[k].nnodes = m->info[k].n_nodes;
       c[k].mode = MODE_DONE;
+      c[k].ngroup = (c[k].ntiles + kArriveGroup - 1) / kArriveGroup;
+      m->max_inst_tiles = std::max(m->max_inst_tiles, c[k].ntiles);
+      c[k].cbase = ncnt;
+      ncnt += c[k].ngroup + 1;
     }
+    const size_t cbytes = size_t(ncnt) * kArriveStride * sizeof(uint32_t);
+    if ((st = dev_alloc(m, cbytes, &tmpp)) != PF_OK) { free_all(m); delete m; return st; }
+    m->dw.arrive = static_cast<uint32_t*>(tmpp);
+    hipError_t ez = hipMemset(m->dw.arrive, 0, cbytes);
+    if (ez != hipSuccess) { free_all(m); delete m; return hip_fail(ez, "hipMemset"); }
     hipError_t e = hipMemcpy(m->dw.ctl, c.data(), sizeof(Ctl) * n_instances, hipMemcpyHostToDevice);
     if (e != hipSuccess) { free_all(m); delete m; return hip_fail(e, "hipMemcpy"); }
   }

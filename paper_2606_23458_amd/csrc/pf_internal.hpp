@@ -84,12 +84,20 @@ struct Ctl {
   int32_t inner;      // CG iterations since the last restart or check
   int32_t wbuf;       // which half of the held-set pair is current
   int32_t outer;      // active-set updates so far
+  int32_t cbase;      // first arrival counter of this instance (counters of 32-tile groups, then the top one)
+  int32_t ngroup;     // 32-tile groups of this instance
   double rz, alpha, beta, amax, resid, pq;
   double ref;         // scale of the stopping test (1 for the damage QP, max |b_i|/A_ii for linear solves)
   double lmax;        // upper bound of the spectrum of D^-1 A (set-up pass; Chebyshev preconditioner)
 };
 
 enum { MODE_RESTART = 0, MODE_ITER = 1, MODE_DONE = 2, MODE_CHECK = 3, MODE_FIRST = 4 };
+
+// Arrival counting of the damage passes: tiles of an instance count in groups
+// of kArriveGroup, the last of each group counts at the instance's top counter.
+// Counters sit kArriveStride uint32 apart (one 128-byte line each).
+constexpr int kArriveGroup = 32;
+constexpr int kArriveStride = 32;
 
 // Device view of a mesh handle.
 struct DevMesh {
@@ -127,6 +135,8 @@ struct DevWork {
   void* hbar;                        // [n_elems] adjoint of H_{n+1} (adjoint step scratch)
   void* mte;                         // [n_te] per-solve mass coefficient (c0 + cH H_e) A_e / 12 of each tile element
   double* part;                      // [n_tiles][8] block partials
+  uint32_t* arrive;                  // arrival counters of the damage passes, kArriveStride apart:
+                                     // per instance one per 32-tile group, then one for the groups
   Ctl* ctl;                          // [n_inst]
   void* instp;                       // [n_inst] InstP<T>
   int* bounds;                       // [n_inst] pf_params_t.bounds of each instance
@@ -146,6 +156,7 @@ struct pf_mesh_s {
   int32_t n_inst = 0, n_nodes = 0, n_elems = 0, n_tiles = 0, n_te = 0;
   int32_t max_tile_nodes = 0, max_tile_elems = 0, max_own = 0, max_lds_explicit = 0, max_lds_damage = 0;
   int32_t max_corner = 0;
+  int32_t max_inst_tiles = 0;        // tiles of the largest instance
   int32_t explicit_block = 256;      // workgroup size of the explicit-step kernel (256 or 512)
   int32_t max_lds_explicit2 = 0;     // LDS of the explicit step with its elements in two chunks
   int32_t explicit_chunks = 0;       // 1, 2, or 0 = automatic

@@ -71,3 +71,31 @@ def test_windowed_run_batched_fp32():
     b.run(20, window=8)
     torch.cuda.synchronize()
     assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
+
+
+@pytest.mark.parametrize("nx,ny", [(96, 48), (256, 128)])
+def test_polled_solve_launches_few_rounds_past_convergence(nx, ny):
+    """A polled solve enqueues as many rounds as the previous solve needed plus two, then
+    polls every check_every rounds: it launches at most its own rounds + check_every + 2
+    passes, also when it needs more rounds than the previous solve (here: a tighter
+    tolerance after a looser one).  The 256x128 plate in 64-node tiles has more tiles than
+    the pass's last workgroup combines itself, so the separate reduction launch is covered."""
+    from paper_2606_23458_amd import CgConfig, Simulator
+    p = w.small_plate(nx, ny, seed=3)
+    sim = Simulator(p, dtype="f64", tile_nodes=64)
+    sim.cg = CgConfig(tol=1e-8, check_every=2)
+    sim.step(3)
+    first = sim.cg_stats()[0]["iters"]
+    sim.cg = CgConfig(tol=1e-13, check_every=2)
+    sim.timer(True)
+    for f in (1, 4):
+        sim.timer_read(f)
+    sim.step()
+    iters = sim.cg_stats()[0]["iters"]
+    _, passes = sim.timer_read(1)
+    _, reductions = sim.timer_read(4)
+    sim.timer(False)
+    assert iters > first + 4, (first, iters)
+    assert iters <= passes <= iters + 2 + 2, (first, iters, passes)
+    many = sim.mesh.totals.n_tiles > 512
+    assert reductions == (passes if many else 0), (reductions, passes, sim.mesh.totals.n_tiles)
