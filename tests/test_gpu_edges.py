@@ -72,6 +72,29 @@ def test_instances_of_very_different_sizes_batched_bitwise():
             assert np.array_equal(got[k][f], ref[f]), (k, f)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_in_pass_combination_equals_reduction_launch_bitwise(dtype):
+    """Instances of up to 512 tiles combine each round's partials in the damage pass's last
+    workgroup; a handle whose largest instance has more tiles uses the separate reduction
+    launch for all of them.  Both combine in the same order, so a small
+    plate batched with a large one (reduction launch) evolves bit for bit like the small plate
+    alone (in-pass combination), over polled and windowed steps."""
+    from paper_2606_23458_amd import Simulator
+    small, large = w.small_plate(40, 20, seed=5), w.small_plate(400, 256, seed=6)
+    both = Simulator([small, large], dtype=dtype, tile_nodes=64)
+    assert max(inf.n_tiles for inf in both.mesh.info) > 512
+    one = Simulator([small], dtype=dtype, tile_nodes=64, dt=[both.dt[0]])
+    assert one.mesh.totals.n_tiles <= 512
+    for sim in (both, one):
+        sim.step(6)
+        sim.run(10)
+    torch.cuda.synchronize()
+    got, ref = both.state.to_user()[0], one.state.to_user()[0]
+    for f in ("u", "v", "a", "d", "H"):
+        assert np.array_equal(got[f], ref[f]), f
+    assert both.cg_stats()[0]["iters"] == one.cg_stats()[0]["iters"]
+
+
 def _solve(p, dtype, H, lb):
     from paper_2606_23458_amd import Simulator, State
     sim = Simulator(p, dtype=dtype, tile_nodes=64)
