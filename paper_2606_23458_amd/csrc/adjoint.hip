@@ -128,24 +128,31 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(const Ctl* ctl, const dou
   if (threadIdx.x == 0) dGc[blockIdx.x] += s;
 }
 
-template <typename T, int S>
+// The tile's elements are processed in nch chunks (1 or 2): each chunk's
+// corner adjoints go to LDS, then every owned node adds the corners of that
+// chunk, continuing its corner list where the previous chunk stopped (the
+// list is in ascending element order, so the sums keep their order; two
+// chunks halve the corner space so that more workgroups share a CU).
+template <typename T, int S, int NPT>
 __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP<T>* __restrict__ ip, StateIn<T> sn,
                                                          StateIn<T> snp1, StateIn<T> adj1,
-                                                         const T* __restrict__ hbar, StateOut<T> adj0, int vfix) {
+                                                         const T* __restrict__ hbar, StateOut<T> adj0, int vfix,
+                                                         int nch) {
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
   const InstP<T> P = ip[t.inst];
   extern __shared__ __align__(16) unsigned char smem[];
   const int nloc = t.n_own + t.n_halo;
+  const int chs = (t.n_telem + nch - 1) / nch;   // elements per chunk
   T* sfx = reinterpret_cast<T*>(smem);   // adjoint of f_int at the tile's nodes
   T* sfy = sfx + nloc;
   T* sux = sfy + nloc;                   // u_{n+1}
   T* suy = sux + nloc;
   T* sd = suy + nloc;                    // d_n
-  T* cux = sd + nloc;                    // corner adjoints of u_{n+1}
-  T* cuy = cux + 3 * t.n_telem;
-  T* cdd = cuy + 3 * t.n_telem;          // corner adjoints of d_n
-  uint16_t* coffs = reinterpret_cast<uint16_t*>(smem + lists_offset((5 * size_t(nloc) + 9 * size_t(t.n_telem)) * sizeof(T)));
+  T* cux = sd + nloc;                    // corner adjoints of u_{n+1} (chunk)
+  T* cuy = cux + 3 * chs;
+  T* cdd = cuy + 3 * chs;                // adjoint of d_n per element (the same for its three corners)
+  uint16_t* coffs = reinterpret_cast<uint16_t*>(smem + lists_offset((5 * size_t(nloc) + 7 * size_t(chs)) * sizeof(T)));
   uint16_t* clist = coffs + t.n_own + 1;
   const int tid = threadIdx.x;
   stage_corners(dm, t, coffs, clist);
@@ -163,55 +170,90 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
     suy[i] = snp1.uy[g];
     sd[i] = sn.d[g];
   }
-  __syncthreads();
-  const T* __restrict__ geo = static_cast<const T*>(dm.geo);
-  const size_t nte = size_t(dm.n_te);
-  for (int e = tid; e < t.n_telem; e += kBlock) {
-    const int te = t.telem_begin + e;
-    const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
-    const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
-    const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
-    const T f0x = sfx[c0], f0y = sfy[c0], f1x = sfx[c1], f1y = sfy[c1], f2x = sfx[c2], f2y = sfy[c2];
-    // f^e_k = A (sxx gkx + sxy gky, sxy gkx + syy gky)
-    T sb[3];
-    sb[0] = A * (f0x * g0x + f1x * g1x + f2x * g2x);
-    sb[1] = A * (f0y * g0y + f1y * g1y + f2y * g2y);
-    sb[2] = A * ((f0x * g0y + f0y * g0x) + (f1x * g1y + f1y * g1x) + (f2x * g2y + f2y * g2x));
-    T exx, eyy, exy;
-    elem_strain<T>(sux[c0], suy[c0], sux[c1], suy[c1], sux[c2], suy[c2], g0x, g0y, g1x, g1y, g2x, g2y, exx, eyy,
-                   exy);
-    T psi_p, sp[3], sm[3];
-    split_eval<S, T>(exx, eyy, exy, P, psi_p, sp, sm);
-    const T de = (sd[c0] + sd[c1] + sd[c2]) / T(3);
-    const T om = T(1) - de;
-    const T gd = om * om + P.eta;
-    const int gid = dm.te_gid[te];
-    const bool won = psi_p > sn.H[gid];
-    const T hb = hbar[gid];
-    T eb[3], gb;
-    split_vjp<S, T>(exx, eyy, exy, gd, sb, won ? hb : T(0), P, eb, gb);
-    const T db = gb * (T(-2) * om) / T(3);
-    cux[3 * e + 0] = eb[0] * g0x + T(0.5) * eb[2] * g0y;
-    cuy[3 * e + 0] = eb[1] * g0y + T(0.5) * eb[2] * g0x;
-    cux[3 * e + 1] = eb[0] * g1x + T(0.5) * eb[2] * g1y;
-    cuy[3 * e + 1] = eb[1] * g1y + T(0.5) * eb[2] * g1x;
-    cux[3 * e + 2] = eb[0] * g2x + T(0.5) * eb[2] * g2y;
-    cuy[3 * e + 2] = eb[1] * g2y + T(0.5) * eb[2] * g2x;
-    cdd[3 * e + 0] = db;
-    cdd[3 * e + 1] = db;
-    cdd[3 * e + 2] = db;
-    if (e >= t.own_elem_lo && e < t.own_elem_lo + t.n_own_elem) adj0.H[gid] = won ? T(0) : hb;
+  // owned nodes' sums, carried across the chunks
+  T ux_r[NPT], uy_r[NPT], dd_r[NPT];
+  int jc[NPT];   // next corner of each owned node
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * kBlock;
+    const int g = t.node_begin + min(i, t.n_own - 1);
+    ux_r[r] = adj1.ux[g];
+    uy_r[r] = adj1.uy[g];
+    dd_r[r] = T(0);
+    jc[r] = 0;
   }
   __syncthreads();
-  for (int i = tid; i < t.n_own; i += kBlock) {
-    const int g = t.node_begin + i;
-    T ux = adj1.ux[g], uy = adj1.uy[g], dd = T(0);
-    for (int j = coffs[i]; j < coffs[i + 1]; ++j) {
-      const int cc = clist[j];
-      ux += cux[cc];
-      uy += cuy[cc];
-      dd += cdd[cc];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * kBlock;
+    if (i < t.n_own) jc[r] = coffs[i];
+  }
+  const T* __restrict__ geo = static_cast<const T*>(dm.geo);
+  const size_t nte = size_t(dm.n_te);
+  for (int e0 = 0; e0 < t.n_telem; e0 += chs) {
+    const int e1 = min(e0 + chs, t.n_telem);
+    if (e0 > 0) __syncthreads();   // the previous chunk's corner adjoints have been added
+    for (int e = e0 + tid; e < e1; e += kBlock) {
+      const int te = t.telem_begin + e;
+      const int c0 = dm.lc0[te], c1 = dm.lc1[te], c2 = dm.lc2[te];
+      const T g0x = geo[te], g0y = geo[nte + te], g1x = geo[2 * nte + te], g1y = geo[3 * nte + te];
+      const T g2x = geo[4 * nte + te], g2y = geo[5 * nte + te], A = geo[6 * nte + te];
+      const T f0x = sfx[c0], f0y = sfy[c0], f1x = sfx[c1], f1y = sfy[c1], f2x = sfx[c2], f2y = sfy[c2];
+      // f^e_k = A (sxx gkx + sxy gky, sxy gkx + syy gky)
+      T sb[3];
+      sb[0] = A * (f0x * g0x + f1x * g1x + f2x * g2x);
+      sb[1] = A * (f0y * g0y + f1y * g1y + f2y * g2y);
+      sb[2] = A * ((f0x * g0y + f0y * g0x) + (f1x * g1y + f1y * g1x) + (f2x * g2y + f2y * g2x));
+      T exx, eyy, exy;
+      elem_strain<T>(sux[c0], suy[c0], sux[c1], suy[c1], sux[c2], suy[c2], g0x, g0y, g1x, g1y, g2x, g2y, exx, eyy,
+                     exy);
+      T psi_p, sp[3], sm[3];
+      split_eval<S, T>(exx, eyy, exy, P, psi_p, sp, sm);
+      const T de = (sd[c0] + sd[c1] + sd[c2]) / T(3);
+      const T om = T(1) - de;
+      const T gd = om * om + P.eta;
+      const int gid = dm.te_gid[te];
+      const bool won = psi_p > sn.H[gid];
+      const T hb = hbar[gid];
+      T eb[3], gb;
+      split_vjp<S, T>(exx, eyy, exy, gd, sb, won ? hb : T(0), P, eb, gb);
+      const int l = e - e0;
+      cux[3 * l + 0] = eb[0] * g0x + T(0.5) * eb[2] * g0y;
+      cuy[3 * l + 0] = eb[1] * g0y + T(0.5) * eb[2] * g0x;
+      cux[3 * l + 1] = eb[0] * g1x + T(0.5) * eb[2] * g1y;
+      cuy[3 * l + 1] = eb[1] * g1y + T(0.5) * eb[2] * g1x;
+      cux[3 * l + 2] = eb[0] * g2x + T(0.5) * eb[2] * g2y;
+      cuy[3 * l + 2] = eb[1] * g2y + T(0.5) * eb[2] * g2x;
+      cdd[l] = gb * (T(-2) * om) / T(3);
+      if (e >= t.own_elem_lo && e < t.own_elem_lo + t.n_own_elem) adj0.H[gid] = won ? T(0) : hb;
     }
+    __syncthreads();
+    // each owned node adds this chunk's corners, in list order
+    const int cend = 3 * e1, cbeg = 3 * e0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int i = tid + r * kBlock;
+      if (i >= t.n_own) continue;
+      const int j1 = coffs[i + 1];
+      int j = jc[r];
+      T ux = ux_r[r], uy = uy_r[r], dd = dd_r[r];
+      for (; j < j1; ++j) {
+        const int cc = clist[j];
+        if (cc >= cend) break;
+        ux += cux[cc - cbeg];
+        uy += cuy[cc - cbeg];
+        dd += cdd[cc / 3 - e0];
+      }
+      jc[r] = j;
+      ux_r[r] = ux, uy_r[r] = uy, dd_r[r] = dd;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int i = tid + r * kBlock;
+    if (i >= t.n_own) continue;
+    const int g = t.node_begin + i;
+    const T ux = ux_r[r], uy = uy_r[r];
     const T vbx = adj1.vx[g], vby = adj1.vy[g];
     // prescribed velocities set by the loading ramp do not depend on v_n
     const uint8_t fl = vfix ? dm.fixed[g] : uint8_t(0);
@@ -221,19 +263,51 @@ __global__ __launch_bounds__(kBlock) void k_adj_explicit(DevMesh dm, const InstP
     adj0.vy[g] = (fl & 2) ? T(0) : vby + P.dt * uy;
     adj0.ax[g] = P.half_dt * vbx + P.half_dt2 * ux;
     adj0.ay[g] = P.half_dt * vby + P.half_dt2 * uy;
-    adj0.d[g] += dd;
+    adj0.d[g] += dd_r[r];
   }
 }
 
-// LDS of an adjoint kernel: nv node values and ne corner values of the mesh
-// dtype per tile (the largest tile of the handle), then the corner lists.
-static size_t adjoint_lds(const pf_mesh_s* m, size_t nv, size_t ne) {
+// LDS of an adjoint kernel: nv node values and ne values per element of the
+// mesh dtype per tile (the largest tile of the handle), its elements taken
+// nch chunks at a time, then the corner lists.
+static size_t adjoint_lds(const pf_mesh_s* m, size_t nv, size_t ne, int nch = 1) {
   size_t vals = 0, lists = 0;
   for (const TileRec& tr : m->tiles_h) {
-    vals = std::max(vals, (nv * size_t(tr.n_own + tr.n_halo) + ne * size_t(tr.n_telem)) * elem_size(m->dtype));
+    const size_t chs = (size_t(tr.n_telem) + size_t(nch) - 1) / size_t(nch);
+    vals = std::max(vals, (nv * size_t(tr.n_own + tr.n_halo) + ne * chs) * elem_size(m->dtype));
     lists = std::max(lists, 2 * (size_t(tr.n_own) + 1 + size_t(tr.n_corner)));
   }
   return lists_offset(vals) + lists + 64;
+}
+
+// LDS of the adjoint kernels and the element chunks of the explicit step's
+// adjoint: two when halving the corner space in LDS lets more workgroups
+// share a CU (capped by the CU's thread slots).  Chosen once per handle.
+static void adjoint_plan(pf_mesh_s* m) {
+  if (m->adj_chunks) return;
+  const size_t l1 = adjoint_lds(m, 5, 7, 1), l2 = adjoint_lds(m, 5, 7, 2);
+  const size_t cap = size_t(std::max(1, m->threads_per_cu / kBlock));
+  const size_t occ1 = std::min(cap, size_t(m->lds_per_cu) / l1), occ2 = std::min(cap, size_t(m->lds_per_cu) / l2);
+  m->adj_chunks = occ2 > occ1 ? 2 : 1;
+  m->adj_lds_explicit = m->adj_chunks == 2 ? l2 : l1;
+  m->adj_lds_damage = adjoint_lds(m, 2, 3);
+}
+
+template <typename T, int S>
+static void launch_adj_explicit(pf_mesh_s* m, const InstP<T>* ip, const StateIn<T>& sn, const StateIn<T>& sn1,
+                                const StateIn<T>& a1, const T* hb, const StateOut<T>& a0, int vfix, hipStream_t s) {
+  const size_t lds = m->adj_lds_explicit;
+  const int nch = m->adj_chunks;
+  const int npt = (m->max_own + kBlock - 1) / kBlock;
+  const dim3 grid(m->n_tiles), block(kBlock);
+  if (npt <= 1)
+    hipLaunchKernelGGL((k_adj_explicit<T, S, 1>), grid, block, lds, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix, nch);
+  else if (npt <= 2)
+    hipLaunchKernelGGL((k_adj_explicit<T, S, 2>), grid, block, lds, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix, nch);
+  else if (npt <= 4)
+    hipLaunchKernelGGL((k_adj_explicit<T, S, 4>), grid, block, lds, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix, nch);
+  else
+    hipLaunchKernelGGL((k_adj_explicit<T, S, 8>), grid, block, lds, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix, nch);
 }
 
 template <typename T>
@@ -252,8 +326,7 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   oa.resume = 0;   // every adjoint solve starts from its own set-up pass
   pf_status_t st = damage_cg(m, CG_LINEAR, s_np1->H, lam, lam, nullptr, nullptr, &oa, stats, s);
   if (st != PF_OK) return st;
-  const size_t lds_d = adjoint_lds(m, 2, 3);
-  const size_t lds_e = adjoint_lds(m, 5, 9);
+  const size_t lds_d = m->adj_lds_damage;
   timer_begin(m, 3, s);
   hipLaunchKernelGGL(k_adj_damage<T>, grid, block, lds_d, s, m->dm, ip, m->dw.part, lam,
                      static_cast<const T*>(s_np1->d), static_cast<const T*>(s_np1->H),
@@ -265,17 +338,10 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   const T* hb = static_cast<const T*>(m->dw.hbar);
   const int vfix = m->ld.vfull != nullptr;
   switch (split) {
-    case SPLIT_NONE:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_NONE>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
-      break;
-    case SPLIT_SPECTRAL:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_SPECTRAL>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
-      break;
-    case SPLIT_VOLDEV:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_VOLDEV>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
-      break;
-    default:
-      hipLaunchKernelGGL((k_adj_explicit<T, SPLIT_STAR>), grid, block, lds_e, s, m->dm, ip, sn, sn1, a1, hb, a0, vfix);
+    case SPLIT_NONE: launch_adj_explicit<T, SPLIT_NONE>(m, ip, sn, sn1, a1, hb, a0, vfix, s); break;
+    case SPLIT_SPECTRAL: launch_adj_explicit<T, SPLIT_SPECTRAL>(m, ip, sn, sn1, a1, hb, a0, vfix, s); break;
+    case SPLIT_VOLDEV: launch_adj_explicit<T, SPLIT_VOLDEV>(m, ip, sn, sn1, a1, hb, a0, vfix, s); break;
+    default: launch_adj_explicit<T, SPLIT_STAR>(m, ip, sn, sn1, a1, hb, a0, vfix, s);
   }
   timer_end(m, 3, s);
   PF_HIP(hipGetLastError());
@@ -305,7 +371,8 @@ extern "C" pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const
   if (opts->precond < 0 || opts->precond > 4) return fail(PF_ERR_ARG, "precond must be in [0, 4]");
   if (states_share(adj_n, adj_np1) || states_share(adj_n, s_n) || states_share(adj_n, s_np1))
     return fail(PF_ERR_ARG, "adj_n shares an array with an input");
-  const size_t lds_e = adjoint_lds(m, 5, 9);
+  adjoint_plan(m);
+  const size_t lds_e = std::max(m->adj_lds_explicit, m->adj_lds_damage);
   int dev = 0, lds_limit = 65536;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds_limit = 65536;

@@ -157,6 +157,9 @@ struct pf_mesh_s {
   int32_t max_tile_nodes = 0, max_tile_elems = 0, max_own = 0, max_lds_explicit = 0, max_lds_damage = 0;
   int32_t max_corner = 0;
   int32_t max_inst_tiles = 0;        // tiles of the largest instance
+  size_t adj_lds_damage = 0;         // LDS of the adjoint kernels (set by the first backward step)
+  size_t adj_lds_explicit = 0;
+  int32_t adj_chunks = 0;            // element chunks of the explicit step's adjoint (0: not yet chosen)
   int32_t explicit_block = 256;      // workgroup size of the explicit-step kernel (256 or 512)
   int32_t max_lds_explicit2 = 0;     // LDS of the explicit step with its elements in two chunks
   int32_t explicit_chunks = 0;       // 1, 2, or 0 = automatic
