@@ -34,9 +34,9 @@ instead).  The same steps are timed with windowed and with polled stepping
                 plate at a time;
 and, unless --no-extras: the explicit step alone, graph-replayed stepping, damage subcycling, the toughness field, the energy kernel, the
 preconditioners, and the explicit step and CG pass on a 2048x1024 plate.
-Tiles hold 512 owned nodes in FP32 and 256 in FP64 (--tile-nodes changes it;
+Tiles hold 512 owned nodes in FP32 and 448 in FP64 (--tile-nodes changes it;
 'auto' lets the autotuner pick the tile size too); the autotuner picks the
-explicit step's workgroup shape.
+explicit step's workgroup shape, the library the damage passes' element chunks.
 """
 from __future__ import annotations
 
@@ -51,7 +51,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-DEFAULT_TILE = {"f32": 512, "f64": 256}
+DEFAULT_TILE = {"f32": 512, "f64": 448}
 WIDTH = {"f32": 4, "f64": 8}
 # Algorithmic bytes per element and launch (paper layout: precomputed grad phi
 # and area, int32 connectivity and corner lists), per arithmetic width w.
@@ -366,7 +366,8 @@ def batched_step(steps: int = 30) -> dict:
     ex = explicit_only(sim, steps, 4)
     return {"workload": f"64 plates 128x64..512x256, {ne} triangles, FP32, one handle",
             "tile_plan": {"tile_nodes": sim.mesh.tile_nodes, "explicit_block": sim.mesh.explicit_block,
-                          "explicit_chunks": sim.mesh.explicit_chunks}, "explicit_step": ex,
+                          "explicit_chunks": sim.mesh.explicit_chunks, "damage_chunks": sim.mesh.damage_chunks},
+            "explicit_step": ex,
             "alg_MB_per_explicit_step": round(alg_bytes_per_elem(0, 4) * ne / 1e6, 1),
             "staggered_ms_per_step": round(ms, 4), "elem_steps_per_s": round(ne / (ms / 1e3), 1)}
 
@@ -657,7 +658,7 @@ def main():
                     help="arithmetic of the headline (FP64 is the paper's)")
     ap.add_argument("--tile-nodes", default=None,
                     help="owned nodes per tile (the autotuner then picks the explicit-step workgroup shape), "
-                         "or 'auto' (the autotuner picks the whole plan); default 512 (FP32), 256 (FP64)")
+                         "or 'auto' (the autotuner picks the whole plan); default 512 (FP32), 448 (FP64)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-protocol", default="bounded", choices=["bounded", "full"])
@@ -713,8 +714,11 @@ def main():
                    "n_elems": res["ne"], "n_nodes": sim.mesh.n_nodes, "precision": prec,
                    "tile_plan": {"tile_nodes": sim.mesh.tile_nodes, "explicit_block": sim.mesh.explicit_block,
                                  "explicit_chunks": sim.mesh.explicit_chunks,
+                                 "damage_chunks": sim.mesh.damage_chunks,
+                                 "n_tiles": int(sim.mesh.totals.n_tiles),
                                  "chosen_by": "autotuner" if tile == "auto"
-                                 else "tile size fixed, workgroup shape by the autotuner"},
+                                 else "tile size fixed, workgroup shape by the autotuner, damage element "
+                                      "chunks by the library"},
                    "stepping": "the faster of Simulator.run (solver convergence read once per 16 steps, window "
                                "re-run on a miss) and Simulator.step (convergence polled in every solve), timed "
                                "on the same steps from fresh simulators; see 'stepping'"},

@@ -96,6 +96,12 @@ typedef struct {
                                 1, 2, or 0 = automatic (2 when halving the
                                 corner-force space in LDS lets more workgroups
                                 share a CU).  The result does not depend on it. */
+    int32_t damage_chunks;   /* element chunks of the damage CG passes per
+                                workgroup: 1, 2, or 0 = automatic (2 when halving
+                                the corner-value space in LDS lets all of a
+                                pass's workgroups be resident at once and one
+                                chunk does not).  The result does not depend
+                                on it. */
 } pf_tile_opts_t;
 
 /* Material and model of one instance (Sec. 2.1-2.2).  Geometry-independent. */
@@ -193,6 +199,7 @@ typedef struct {
     int32_t max_tile_nodes, max_tile_elems;
     int32_t tile_elems_total;        /* element records incl. halo copies */
     size_t device_bytes;             /* device memory held by the handle */
+    int32_t damage_chunks;           /* element chunks of the damage passes (1, 2) */
 } pf_mesh_totals_t;
 
 /*
@@ -419,7 +426,7 @@ enum { PF_TUNE_MAX = 8 };
 
 typedef struct {
     int32_t n_candidates;        /* entries of tile_nodes[] to try, 0..8; 0 = the default set
-                                    {128, 192, 256, 384, 512, 768, 1024} */
+                                    {128, 192, 256, 384, 448, 512, 768, 1024} */
     int32_t tile_nodes[PF_TUNE_MAX];
     int32_t reps;                /* timed launches per candidate, 0..10000; 0 = 20 */
     double cg_rounds_per_step;   /* weight of one CG round in the score; <= 0 selects 16 */

@@ -29,7 +29,8 @@ class MeshDesc(C.Structure):
 
 
 class TileOpts(C.Structure):
-    _fields_ = [("tile_nodes", C.c_int32), ("explicit_block", C.c_int32), ("explicit_chunks", C.c_int32)]
+    _fields_ = [("tile_nodes", C.c_int32), ("explicit_block", C.c_int32), ("explicit_chunks", C.c_int32),
+                ("damage_chunks", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -61,7 +62,8 @@ class InstanceInfo(C.Structure):
 class Totals(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("n_nodes", C.c_int32), ("n_elems", C.c_int32),
                 ("n_tiles", C.c_int32), ("dtype", C.c_int32), ("max_tile_nodes", C.c_int32),
-                ("max_tile_elems", C.c_int32), ("tile_elems_total", C.c_int32), ("device_bytes", C.c_size_t)]
+                ("max_tile_elems", C.c_int32), ("tile_elems_total", C.c_int32), ("device_bytes", C.c_size_t),
+                ("damage_chunks", C.c_int32)]
 
 
 PF_TUNE_MAX = 8

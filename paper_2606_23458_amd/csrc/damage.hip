@@ -57,6 +57,7 @@
 // other, so halo reads never race with the owners' writes.  No floating-point
 // atomics and no device-wide fences are used.  Linear mode (CG_LINEAR) solves
 // A_FF x_F = b_F for a fixed held set and is used by the adjoint step.
+#include <climits>
 #include <cstring>
 
 #include "device_common.hpp"
@@ -109,6 +110,7 @@ struct DmgArgs {
   // 2 combine and run the state machine without storing it (timing aid)
   int32_t fuse;
   uint32_t* arrive;    // arrival counters (see kArriveGroup)
+  int32_t nch;         // element chunks of a pass (1, 2): the corner-value space holds 3 / nch values per element
 };
 
 // Chebyshev-Jacobi preconditioner z = p(D^-1 A) D^-1 r: `cheb` steps of the
@@ -174,7 +176,7 @@ __device__ __forceinline__ T clamp01(T v, T lo) {
   return v < lo ? lo : (v > T(1) ? T(1) : v);
 }
 
-template <typename T, int NPT, bool CHEB, bool FUSE>
+template <typename T, int NPT, bool CHEB, bool FUSE, int NCH>
 __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[8 * 4 * kWaves];
   const int tile = tile_of_block(a.dm.n_tiles);
@@ -385,13 +387,13 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     T dacc[NPT], bacc[NPT], sacc[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) dacc[r] = T(0), bacc[r] = T(0), sacc[r] = T(0);
-    // two chunks: 4 values of width w per element in two halves fit the 3
-    // values per element of an iteration pass (chunk sizes depend only on the
-    // tile, so the sums are the same in a batched and a single-instance handle;
-    // chunks split each node's corner sequence without reordering it).  The
+    // 2 nch chunks: 4 values of width w per element fit the 3 / nch values per
+    // element of the corner space (chunks split each node's corner sequence
+    // without reordering it, so the sums do not depend on the chunking).  The
     // Chebyshev preconditioner also needs the absolute row sums of the element
-    // matrices (7 values per element): four chunks.
-    const int chs = CHEB ? (t.n_telem + 3) / 4 : (t.n_telem + 1) / 2;
+    // matrices (7 values per element): 4 nch chunks.
+    const int nsc = (CHEB ? 4 : 2) * NCH;
+    const int chs = (t.n_telem + nsc - 1) / nsc;
     T* sc_ = dc + 4 * chs;   // [3 chunk] absolute row sums per corner (Chebyshev)
     for (int e0 = 0; e0 < t.n_telem; e0 += chs) {
       const int e1 = min(e0 + chs, t.n_telem);
@@ -461,9 +463,10 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     double qacc[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) qacc[r] = 0.0;
-    // FP64 corner values: two chunks in FP32 (3 doubles per element in the
-    // space of 6 floats), one in FP64
-    const int chx = sizeof(T) == 4 ? (t.n_telem + 1) / 2 : t.n_telem;
+    // FP64 corner values: 2 nch chunks in FP32 (3 doubles per element in the
+    // space of 6 floats), nch in FP64
+    const int nxc = (sizeof(T) == 4 ? 2 : 1) * NCH;
+    const int chx = (t.n_telem + nxc - 1) / nxc;
     for (int e0 = 0; e0 < t.n_telem; e0 += chx) {
       const int e1 = min(e0 + chx, t.n_telem);
       __syncthreads();
@@ -544,20 +547,55 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
     }
   } else {
     // ---- first / iterate: corner values of A^e z^e in T ----------------------
-    __syncthreads();
-    for (int e = tid; e < t.n_telem; e += kBlock) {
-      const int te = t.telem_begin + e;
-      const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
-      const T w01 = kw[te], w02 = kw[nte + te], w12 = kw[2 * nte + te];
-      const T kp = P.kap * (gcs ? gcs[te] : T(1));
-      const T mA = a.mte[te];
-      const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
-      const T ss = s0 + s1 + s2;
-      qc[3 * e + 0] = kp * (w01 * (s1 - s0) + w02 * (s2 - s0)) + mA * (s0 + ss);
-      qc[3 * e + 1] = kp * (w01 * (s0 - s1) + w12 * (s2 - s1)) + mA * (s1 + ss);
-      qc[3 * e + 2] = kp * (w02 * (s0 - s2) + w12 * (s1 - s2)) + mA * (s2 + ss);
+    // NCH chunks of the tile's elements; each owned node adds the chunk's
+    // entries of its corner list (ascending) from where the previous chunk
+    // stopped, so every node's sum runs in the same order for any NCH
+    T qacc[NPT];
+    int jc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) qacc[r] = T(0);
+    const int che = NCH == 1 ? t.n_telem : (t.n_telem + NCH - 1) / NCH;
+#pragma unroll 1
+    for (int e0 = 0; e0 < t.n_telem; e0 += che) {
+      const int e1 = min(e0 + che, t.n_telem);
+      __syncthreads();
+      for (int e = e0 + tid; e < e1; e += kBlock) {
+        const int te = t.telem_begin + e;
+        const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
+        const T w01 = kw[te], w02 = kw[nte + te], w12 = kw[2 * nte + te];
+        const T kp = P.kap * (gcs ? gcs[te] : T(1));
+        const T mA = a.mte[te];
+        const T s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
+        const T ss = s0 + s1 + s2;
+        const int l = e - e0;
+        qc[3 * l + 0] = kp * (w01 * (s1 - s0) + w02 * (s2 - s0)) + mA * (s0 + ss);
+        qc[3 * l + 1] = kp * (w01 * (s0 - s1) + w12 * (s2 - s1)) + mA * (s1 + ss);
+        qc[3 * l + 2] = kp * (w02 * (s0 - s2) + w12 * (s1 - s2)) + mA * (s2 + ss);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NPT; ++r) {
+        const int i = tid + r * kBlock;
+        if (i >= t.n_own) continue;
+        const int j1 = coffs[i + 1];
+        if constexpr (NCH == 1) {
+          T q = T(0);
+          for (int j = coffs[i]; j < j1; ++j) q += qc[clist[j]];
+          qacc[r] = q;
+        } else {
+          const int cend = 3 * e1, cbeg = 3 * e0;
+          int j = (e0 == 0) ? int(coffs[i]) : jc[r];
+          T q = qacc[r];
+          for (; j < j1; ++j) {
+            const int cc = clist[j];
+            if (cc >= cend) break;
+            q += qc[cc - cbeg];
+          }
+          qacc[r] = q;
+          jc[r] = j;
+        }
+      }
     }
-    __syncthreads();
     T* wn = iter ? wn_ : (cur1 ? a.w1 : a.w0);
     const T* rz = iter ? rn_ : rc;
     T* ydst = (stage & 1) ? a.y1 : a.y0;
@@ -566,9 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       const int i = tid + r * kBlock;
       if (i >= t.n_own) continue;
       const int g = t.node_begin + i;
-      const int j0 = coffs[i], j1 = coffs[i + 1];
-      T qi = T(0);
-      for (int j = j0; j < j1; ++j) qi += qc[clist[j]];
+      const T qi = qacc[r];
       if (CHEB && stage < a.cheb - 1) {
         // Chebyshev step stage + 1: qi = A y_j; d_j and y_{j+1} = y_j + d_j (0 on held nodes)
         const uint8_t w = fast ? wf_r[r] : Wc[g];
@@ -962,15 +998,63 @@ static DmgArgs<T> dmg_args(pf_mesh_s* m, int kind, const void* H, const void* d_
   a.stage = 0;
   a.fuse = 0;
   a.arrive = m->dw.arrive;
+  a.nch = 1;
   return a;
 }
 
 // The damage pass for npt owned nodes per thread (a tile of up to 256 npt
-// owned nodes).
+// owned nodes) with its elements in nch chunks.
+template <typename T, int NPT, bool CHEB, bool FUSE>
+static void (*dmg_kernel_c(int nch))(DmgArgs<T>) {
+  return nch == 2 ? k_dmg<T, NPT, CHEB, FUSE, 2> : k_dmg<T, NPT, CHEB, FUSE, 1>;
+}
 template <typename T, bool CHEB, bool FUSE>
-static void (*dmg_kernel(int npt))(DmgArgs<T>) {
-  return npt <= 1 ? k_dmg<T, 1, CHEB, FUSE>
-                  : (npt <= 2 ? k_dmg<T, 2, CHEB, FUSE> : (npt <= 4 ? k_dmg<T, 4, CHEB, FUSE> : k_dmg<T, 8, CHEB, FUSE>));
+static void (*dmg_kernel(int npt, int nch))(DmgArgs<T>) {
+  return npt <= 1 ? dmg_kernel_c<T, 1, CHEB, FUSE>(nch)
+                  : (npt <= 2 ? dmg_kernel_c<T, 2, CHEB, FUSE>(nch)
+                              : (npt <= 4 ? dmg_kernel_c<T, 4, CHEB, FUSE>(nch) : dmg_kernel_c<T, 8, CHEB, FUSE>(nch)));
+}
+
+// Element chunks of the damage passes: two when halving the corner-value
+// space in LDS lets every tile's workgroup be resident at once where one
+// chunk cannot (the workgroups per CU from the kernel's registers and LDS).
+// A second wave that holds only the tiles the first could not place moves a
+// fraction of the pass's bytes but adds most of a pass's latency; with
+// several waves either way the second chunk's extra barrier and element
+// phase cost more than the shorter tail saves.
+template <typename T>
+static int damage_chunks(pf_mesh_s* m) {
+  if (m->dmg_nch > 0) return m->dmg_nch;
+  int nch = m->damage_chunks;
+  if (nch <= 0) {
+    const int npt = (m->max_own + kBlock - 1) / kBlock;
+    const void* k1 = reinterpret_cast<const void*>(dmg_kernel<T, false, false>(npt, 1));
+    const void* k2 = reinterpret_cast<const void*>(dmg_kernel<T, false, false>(npt, 2));
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    auto waves = [&](const void* k, size_t lds) -> long {
+      int occ = 0;
+      if (ncu <= 0 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kBlock, lds) != hipSuccess || occ <= 0)
+        return LONG_MAX;
+      const long slots = long(occ) * ncu;
+      return (long(m->n_tiles) + slots - 1) / slots;
+    };
+    nch = (waves(k2, size_t(m->max_lds_damage2)) == 1 && waves(k1, size_t(m->max_lds_damage)) > 1) ? 2 : 1;
+  }
+  m->dmg_nch = nch;
+  return nch;
+}
+
+void damage_plan(pf_mesh_s* m) {
+  if (m->dtype == PF_F64)
+    (void)damage_chunks<double>(m);
+  else
+    (void)damage_chunks<float>(m);
+}
+
+static size_t damage_lds(const pf_mesh_s* m, int nch) {
+  return size_t(nch == 2 ? m->max_lds_damage2 : m->max_lds_damage);
 }
 
 template <typename T>
@@ -979,7 +1063,8 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
                              pf_cg_stats_t* stats, hipStream_t s) {
   DmgArgs<T> a = dmg_args<T>(m, kind, H, d_prev, d, guess, o->tol, o->max_iter, o->start);
   const dim3 grid(m->n_tiles), block(kBlock), igrid(m->n_inst);
-  const size_t lds = m->max_lds_damage;
+  a.nch = damage_chunks<T>(m);
+  const size_t lds = damage_lds(m, a.nch);
   if (!o->resume) {
     timer_begin(m, 2, s);
     hipLaunchKernelGGL(k_dmg_init, dim3((m->n_inst + 63) / 64), dim3(64), 0, s, m->dw.ctl, m->n_inst, kind,
@@ -999,8 +1084,8 @@ static pf_status_t run_solve(pf_mesh_s* m, int kind, const void* H, const void* 
   a.y0 = static_cast<T*>(m->dw.y0);
   a.y1 = static_cast<T*>(m->dw.y1);
   a.dv = static_cast<T*>(m->dw.dv);
-  auto kdmg = cheb ? dmg_kernel<T, true, false>(npt)
-                   : (a.fuse ? dmg_kernel<T, false, true>(npt) : dmg_kernel<T, false, false>(npt));
+  auto kdmg = cheb ? dmg_kernel<T, true, false>(npt, a.nch)
+                   : (a.fuse ? dmg_kernel<T, false, true>(npt, a.nch) : dmg_kernel<T, false, false>(npt, a.nch));
   if (kind == CG_QP) {
     const unsigned char* ab = reinterpret_cast<const unsigned char*>(&a);
     m->last_qp_args.assign(ab, ab + sizeof(a));
@@ -1094,10 +1179,10 @@ static pf_status_t repeat_pass(pf_mesh_s* m, const void* H, const void* d_prev, 
     if (m->ctl_pinned[k].mode != MODE_ITER)
       return fail(PF_ERR_ARG, "the last damage solve did not stop in a CG iteration");
   const int npt = (m->max_own + kBlock - 1) / kBlock;
-  auto kdmg = a.fuse ? dmg_kernel<T, false, true>(npt) : dmg_kernel<T, false, false>(npt);
+  auto kdmg = a.fuse ? dmg_kernel<T, false, true>(npt, a.nch) : dmg_kernel<T, false, false>(npt, a.nch);
   a.stage = 0;
   for (int i = 0; i < n; ++i)
-    hipLaunchKernelGGL(kdmg, dim3(m->n_tiles), dim3(kBlock), m->max_lds_damage, s, a);
+    hipLaunchKernelGGL(kdmg, dim3(m->n_tiles), dim3(kBlock), damage_lds(m, a.nch), s, a);
   PF_HIP(hipGetLastError());
   return PF_OK;
 }

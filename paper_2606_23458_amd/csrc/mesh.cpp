@@ -265,6 +265,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   if (explicit_block != 256 && explicit_block != 512) return fail(PF_ERR_ARG, "explicit_block must be 256 or 512");
   const int explicit_chunks = tile ? tile->explicit_chunks : 0;
   if (explicit_chunks < 0 || explicit_chunks > 2) return fail(PF_ERR_ARG, "explicit_chunks must be 0, 1 or 2");
+  const int damage_chunks = tile ? tile->damage_chunks : 0;
+  if (damage_chunks < 0 || damage_chunks > 2) return fail(PF_ERR_ARG, "damage_chunks must be 0, 1 or 2");
 
   // ---- validate and count -------------------------------------------------
   int64_t n_tot = 0, e_tot = 0;
@@ -283,6 +285,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   m->dtype = dtype;
   m->explicit_block = explicit_block;
   m->explicit_chunks = explicit_chunks;
+  m->damage_chunks = damage_chunks;
   m->n_inst = n_instances;
   m->n_nodes = int32_t(n_tot);
   m->n_elems = int32_t(e_tot);
@@ -676,6 +679,8 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   m->max_lds_explicit = int32_t((3 * size_t(max_loc) + 6 * size_t(max_te)) * w + lists + 64);
   m->max_lds_explicit2 = int32_t((3 * size_t(max_loc) + 6 * ((size_t(max_te) + 1) / 2)) * w + lists + 64);
   m->max_lds_damage = int32_t(((size_t(max_loc) * w + lists + 7) & ~size_t(7)) + size_t(max_te) * 3 * w + 64);
+  m->max_lds_damage2 =
+      int32_t(((size_t(max_loc) * w + lists + 7) & ~size_t(7)) + ((size_t(max_te) + 1) / 2) * 3 * w + 64);
   int dev = 0, lds_limit = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_limit <= 0)
@@ -695,6 +700,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
     return fail(PF_ERR_UNSUPPORTED, s);
   }
   m->device = dev;
+  damage_plan(m);
   // device address of the static partials of pf_energies_static on this device
   if ((st = energy_scratch_setup(dev)) != PF_OK) { free_all(m); delete m; return st; }
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
@@ -722,6 +728,7 @@ extern "C" pf_status_t pf_mesh_totals(pf_mesh_t m, pf_mesh_totals_t* out) {
   out->max_tile_elems = m->max_tile_elems;
   out->tile_elems_total = m->n_te;
   out->device_bytes = m->device_bytes;
+  out->damage_chunks = m->dmg_nch;
   return PF_OK;
 }
 

@@ -163,6 +163,9 @@ struct pf_mesh_s {
   int32_t explicit_block = 256;      // workgroup size of the explicit-step kernel (256 or 512)
   int32_t max_lds_explicit2 = 0;     // LDS of the explicit step with its elements in two chunks
   int32_t explicit_chunks = 0;       // 1, 2, or 0 = automatic
+  int32_t max_lds_damage2 = 0;       // LDS of the damage passes with their elements in two chunks
+  int32_t damage_chunks = 0;         // as requested: 1, 2, or 0 = automatic
+  int32_t dmg_nch = 0;               // element chunks of the damage passes (0: not yet chosen)
   int32_t lds_per_cu = 160 * 1024;   // device limits that set how many workgroups share a CU
   int32_t threads_per_cu = 2048;
   int32_t split = -1;
@@ -229,6 +232,8 @@ pf_status_t check_state(const pf_state_t* s, bool need_d, bool need_H, const cha
 // Resolve, once per device (that device current), the device address of the
 // static partials array of pf_energies_static (energy.hip).
 pf_status_t energy_scratch_setup(int device);
+// Choose the element chunks of the damage passes for this handle (damage.hip).
+void damage_plan(pf_mesh_s* m);
 bool states_share(const pf_state_t* a, const pf_state_t* b);
 
 }  // namespace pf

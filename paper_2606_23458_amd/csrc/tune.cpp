@@ -32,14 +32,14 @@ struct Events {
   }
 };
 
-constexpr int kDefaultCandidates[] = {128, 192, 256, 384, 512, 768, 1024};
+constexpr int kDefaultCandidates[] = {128, 192, 256, 384, 448, 512, 768, 1024};
 
 // Time `reps` explicit steps and `reps` damage CG rounds of one tile plan.
 pf_status_t time_plan(const pf_mesh_desc_t* inst, int32_t n_inst, pf_dtype_t dtype, const pf_params_t* p,
                       int32_t tile_nodes, int32_t reps, hipStream_t s, double* explicit_us, int32_t* explicit_block,
                       int32_t* explicit_chunks, double* round_us) {
   Handle h;
-  pf_tile_opts_t to{tile_nodes, 0, 0};
+  pf_tile_opts_t to{tile_nodes, 0, 0, 0};
   pf_status_t st = pf_mesh_create(inst, n_inst, dtype, &to, s, &h.m);
   if (st != PF_OK) return st;
   pf_mesh_s* m = h.m;

@@ -37,7 +37,7 @@ class Mesh:
     """
 
     def __init__(self, meshes, dtype: str = "f64", tile_nodes: int = 0, device: str = "cuda",
-                 explicit_block: int = 0, explicit_chunks: int = 0):
+                 explicit_block: int = 0, explicit_chunks: int = 0, damage_chunks: int = 0):
         if dtype not in ("f32", "f64"):
             raise ValueError(dtype)
         self.dtype_code = dtype
@@ -57,13 +57,14 @@ class Mesh:
             descs[k] = L.MeshDesc(len(xy), len(tri), xy.ctypes.data, tri.ctypes.data,
                                   None if fx is None else fx.ctypes.data)
         h = C.c_void_p()
-        opts = L.TileOpts(int(tile_nodes), int(explicit_block), int(explicit_chunks))
+        opts = L.TileOpts(int(tile_nodes), int(explicit_block), int(explicit_chunks), int(damage_chunks))
         L.call("pf_mesh_create", descs, n, L.PF_F64 if dtype == "f64" else L.PF_F32, C.byref(opts),
                _stream(), C.byref(h))
         self.handle = h
         tot = L.Totals()
         L.call("pf_mesh_totals", h, C.byref(tot))
         self.totals = tot
+        self.damage_chunks = int(tot.damage_chunks)   # as chosen by the library
         self.n_instances, self.n_nodes, self.n_elems = tot.n_instances, tot.n_nodes, tot.n_elems
         self.info = []
         for k in range(n):

@@ -68,3 +68,25 @@ def test_explicit_element_chunks_agree_bitwise(block):
     b.step(8)
     torch.cuda.synchronize()
     assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
+
+
+@pytest.mark.parametrize("dtype,tile,precond,monotone", [("f64", 256, 0, 0), ("f32", 512, 0, 0), ("f64", 512, 0, 1),
+                                                         ("f32", 256, 3, 0)])
+def test_damage_element_chunks_agree_bitwise(dtype, tile, precond, monotone):
+    """One or two element chunks per damage pass add each node's corner values in the same order:
+    the same bits in every pass type (set-up, restart / check, first / iterate, Chebyshev)."""
+    from paper_2606_23458_amd import Mesh, Simulator
+    from paper_2606_23458_amd.sim import CgConfig, default_tol
+    p = w.small_plate(64, 32, seed=3)
+    cg = CgConfig(tol=default_tol(dtype), precond=precond, monotone=monotone)
+    ma = Mesh([p], dtype, tile, damage_chunks=1)
+    mb = Mesh([p], dtype, tile, damage_chunks=2)
+    assert (ma.damage_chunks, mb.damage_chunks) == (1, 2)
+    a = Simulator(p, dtype=dtype, mesh=ma, cg=cg)
+    b = Simulator(p, dtype=dtype, mesh=mb, dt=list(a.dt), cg=cg)
+    for _ in range(10):
+        a.step()
+        b.step()
+        assert a.cg_stats()[0]["iters"] == b.cg_stats()[0]["iters"]
+    torch.cuda.synchronize()
+    assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
