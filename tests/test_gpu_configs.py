@@ -8,6 +8,9 @@
     a short window of staggered steps; the damage must agree to 1e-4 at every
     node (the FP32 bar), the mechanics to FP32 rounding accumulated over the
     window;
+  - the 1024x512 plate in FP64 in the launch configuration of the headline
+    measurement: an explicit step element by element and a short window of
+    staggered steps against the oracle at the FP64 bar;
   - the 64-plate inverse workload in FP32: the batched reverse sweep gives
     each instance the dL/dGc of its own single-instance handle.
 """
@@ -95,6 +98,49 @@ def test_fp32_trajectory_window_matches_oracle(name):
         assert dd <= 1e-4, (name, k, dd)
         assert eu < 1e-5 and ev < 1e-4 and eh < 1e-4, (name, k, eu, ev, eh)
     assert got["d"].max() > 0.0
+
+
+def test_fp64_headline_configuration_matches_oracle():
+    """The FP64 headline as bench.py times it (1024x512 plate, 448-node tiles, the damage passes'
+    elements in two chunks): one explicit step from a random state element by element, then,
+    after 300 GPU steps, two staggered steps of the GPU and the oracle from the same state; the
+    damage agrees to 1e-9 at every node and the mechanics to 1e-9 relative (the FP64 bar)."""
+    from paper_2606_23458_amd import Simulator, State
+    from tests.gpu_common import random_state, to_oracle
+    p = w.config1()
+    osim0 = OSim(p)
+    sim = Simulator(p, dtype="f64", tile_nodes=448, dt=[osim0.dt])
+    # with one chunk 4 workgroups fit a CU (1024 < 1174 tiles), with two all of them
+    assert sim.mesh.damage_chunks == 2 and sim.mesh.totals.n_tiles == 1174
+    st = random_state(p, seed=37)
+    s_in = State.from_user(sim.mesh, [st])
+    s_out = State(sim.mesh)
+    sim.explicit(s_in, s_out)
+    torch.cuda.synchronize()
+    got = s_out.to_user()[0]
+    u1, v1, a1, H1, _ = osim0.explicit(to_oracle(st))
+    for f, ref in (("u", u1), ("v", v1), ("a", a1), ("H", H1)):
+        assert rel_err(got[f], ref.numpy()) < 1e-12, f
+    del osim0
+    sim.reset()
+    sim.run(300)
+    torch.cuda.synchronize()
+    start = sim.state.to_user()[0]
+    assert np.sum((start["d"] > 1e-3) & (start["d"] < 1.0)) > 100
+    osim = OSim(p, dt=sim.dt[0])
+    f = lambda x: torch.as_tensor(np.asarray(x, dtype=np.float64)).clone()
+    ost = OState(f(start["u"]), f(start["v"]), f(start["a"]), f(start["d"]), f(start["H"]))
+    for k in range(2):
+        sim.step()
+        ost = osim.step(ost)
+        torch.cuda.synchronize()
+        got = sim.state.to_user()[0]
+        assert sim.cg_stats()[0]["flags"] == 0
+        dd = float(np.max(np.abs(got["d"] - ost.d.numpy())))
+        errs = {fld: rel_err(got[fld], getattr(ost, fld).numpy()) for fld in ("u", "v", "a", "H")}
+        print(f"FP64 step {301 + k}: max|d - d_oracle| {dd:.2e}, rel {errs}", flush=True)
+        assert dd <= 1e-9, (k, dd)
+        assert max(errs.values()) < 1e-9, (k, errs)
 
 
 def test_batched_fp32_backward_equals_single_instances():
