@@ -103,6 +103,10 @@ def test_argument_errors():
     h = C.c_void_p()
     assert lib.pf_mesh_create(descs, 1, 0, C.byref(L.TileOpts(0, 384)), None, C.byref(h)) == L.PF_ERR_ARG
     assert "explicit_block" in lib.pf_last_error().decode()
+    assert lib.pf_mesh_create(descs, 1, 0, C.byref(L.TileOpts(0, 0, 3)), None, C.byref(h)) == L.PF_ERR_ARG
+    assert "explicit_chunks" in lib.pf_last_error().decode()
+    assert lib.pf_mesh_create(descs, 1, 0, C.byref(L.TileOpts(0, 0, 0, 3)), None, C.byref(h)) == L.PF_ERR_ARG
+    assert "damage_chunks" in lib.pf_last_error().decode()
     assert lib.pf_mesh_create(None, 1, 0, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_explicit_step(None, None, None, None, None, None, None) == L.PF_ERR_ARG
     assert lib.pf_damage_solve(None, None, None, None, None, None, None, None, None, None) == L.PF_ERR_ARG
