@@ -45,7 +45,11 @@
 //                iterate: the vector updates above and w = A z, where each
 //                  tile recomputes z on its halo nodes from the previous
 //                  vectors, so no second pass is needed;
-//              and per-tile partial sums;
+//              and per-tile partial sums.  A pass takes its tile's elements
+//              in one or two chunks (the corner values of a chunk in LDS,
+//              each owned node adding them in its corner-list order), two
+//              where that lets every workgroup of the pass be resident at
+//              once (damage_chunks);
 //   k_dmg_red  one workgroup per instance combines its tiles' partials in a
 //              fixed order (bitwise reproducible results) and advances the
 //              instance's state.
