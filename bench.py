@@ -15,7 +15,8 @@ instead).  The same steps are timed with windowed and with polled stepping
                 iterate passes of a solve stopped mid-iteration, with the
                 in-solve figure from HIP events around each launch beside it),
                 the byte basis, and the measured HBM traffic of that pass from
-                the committed counter summary;
+                the committed counter summary; also its fraction of a plain
+                1 GiB device copy timed on the same box (copy_kernel);
   cpu_baseline  the FP64 CPU oracle on one pinned core: the headline plate
                 (one warm-up step, two timed), the 64x32 plate in full, the
                 perforated plate and four plates of the 64-plate workload
@@ -276,6 +277,28 @@ def damage_pass_b2b(sim, passes: int = 100, reps: int = 3) -> float | None:
         gpu_sync()
         ts.append(ev0.elapsed_time(ev1) / passes / 1e3)
     return sum(ts) / len(ts)
+
+
+def copy_bandwidth(mib: int = 1024, reps: int = 10) -> dict:
+    """A plain device-to-device copy (the runtime's copy kernel) of `mib` MiB, beyond the
+    Infinity Cache, timed with HIP events over `reps` copies: what a streaming kernel reaches on
+    this box, beside the 8 TB/s specification."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    ev0, ev1 = events()
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    gpu_sync()
+    t = ev0.elapsed_time(ev1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"MiB": mib, "bytes_per_copy": 2 * n, "GBps": round(2 * n / t / 1e9, 1), "reps": reps}
 
 
 def roofline(res) -> dict:
@@ -728,6 +751,10 @@ def main():
     }
     res["b2b_s"] = damage_pass_b2b(sim)
     out["roofline"] = roofline(res)
+    cp = copy_bandwidth()
+    out["roofline"]["copy_kernel_GBps"] = cp["GBps"]
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / cp["GBps"], 4)
+    out["copy_kernel"] = cp
     # keep the contract's key order: roofline right after the config
     order = list(out)
     order.remove("roofline")
