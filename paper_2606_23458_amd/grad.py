@@ -55,9 +55,14 @@ class TrajectoryRunner:
         # a checkpoint keeps the state, the held flags and the previous damage
         # field (the damage solve extrapolates from it)
         self.checkpoints = [(sim.state.clone(), sim.active.clone(), sim._next.d.clone())]
+        # the CG round count of every solve: a segment's recompute repeats its
+        # solves bit for bit, so it enqueues exactly these rounds
+        self.seg_rounds: list[list[int]] = []
         for n0 in range(0, self.steps, self.K):
             k = min(self.K, self.steps - n0)
-            sim.run(k, window=min(k, 25))
+            rounds: list[int] = []
+            sim.run(k, window=min(k, 25), rounds_out=rounds)
+            self.seg_rounds.append(rounds if len(rounds) == k else [])
             if n0 + k < self.steps:
                 self.checkpoints.append((sim.state.clone(), sim.active.clone(), sim._next.d.clone()))
         return sim.state
@@ -105,7 +110,7 @@ class TrajectoryRunner:
             self.seg_active[0].copy_(ck_active)
             tm = self._timing
             t0 = self._clock() if tm is not None else 0.0
-            self._recompute(k1 - k0, ck_dprev)
+            self._recompute(k1 - k0, ck_dprev, self.seg_rounds[sgi] if sgi < len(self.seg_rounds) else [])
             t1 = self._clock() if tm is not None else 0.0
             cur, nxt = self._reverse(k1 - k0, cur, nxt, dGc)
             if tm is not None:
@@ -116,26 +121,32 @@ class TrajectoryRunner:
         return dGc
 
 
-    # The recompute enqueues every step with a fixed budget of CG rounds and
-    # reads the solvers' statistics once at the end; a segment whose solves
-    # did not all finish is recomputed with convergence polling.
+    # The recompute enqueues every step with the CG rounds its solve took in
+    # the forward sweep (else a fixed budget) and reads the solvers'
+    # statistics once at the end; a segment whose solves did not all finish
+    # is recomputed with convergence polling.
     def _stats(self, n: int) -> torch.Tensor:
         ni = self.sim.mesh.n_instances
         if getattr(self, "_seg_stats", None) is None or self._seg_stats.shape[0] < n:
             self._seg_stats = torch.zeros((n, ni * 6), dtype=torch.int32, device=self.sim.mesh.device)
         return self._seg_stats
 
-    def _recompute(self, n: int, dprev0: torch.Tensor) -> None:
+    def _recompute(self, n: int, dprev0: torch.Tensor, rounds: list[int]) -> None:
         sim, states, act = self.sim, self.seg_states, self.seg_active
         stats = self._stats(n)
         budget = getattr(self, "_fwd_budget", 0) or 32
-        o = sim.cg.__class__(sim.cg.tol, sim.cg.max_iter, 0, sim.cg.start, sim.cg.monotone,
-                             min(budget, sim.cg.max_iter), 0, sim.cg.precond)
+        c = sim.cg
+
+        def opts(r: int):
+            return c.__class__(c.tol, c.max_iter, 0, c.start, c.monotone, min(max(r, 1), c.max_iter), 0, c.precond)
+
+        o = opts(budget)
+        exact = len(rounds) == n
         for j in range(n):
             states[j + 1].d.copy_(dprev0 if j == 0 else states[j - 1].d)
             sim.explicit(states[j], states[j + 1])
-            sim.damage(states[j + 1].H, states[j].d, states[j + 1].d, act[j + 1], act[j], cg=o,
-                       stats=stats[j])
+            sim.damage(states[j + 1].H, states[j].d, states[j + 1].d, act[j + 1], act[j],
+                       cg=opts(rounds[j]) if exact else o, stats=stats[j])
         st = stats[:n].cpu().numpy().reshape(n, -1, 6)
         if np.any(st[:, :, 3] != 0):
             for j in range(n):

@@ -379,18 +379,22 @@ class Simulator:
         self.explicit(s_in, s_out, f_ext)
         s_out.d.copy_(s_in.d)
 
-    def step(self, n: int = 1) -> State:
+    def step(self, n: int = 1, rounds_out: list | None = None) -> State:
+        """n staggered steps, each damage solve polled for convergence; rounds_out, if given,
+        receives each solve's CG round count (the largest over the instances)."""
         for _ in range(n):
             if self.solves_at(self.steps_done):
                 self.step_into(self.state, self._next, self._active_next, self.active)
                 self.active, self._active_next = self._active_next, self.active
+                if rounds_out is not None:
+                    rounds_out.append(max(s["iters"] for s in self.cg_stats()))
             else:
                 self.skip_into(self.state, self._next)
             self.state, self._next = self._next, self.state
             self.steps_done += 1
         return self.state
 
-    def run(self, n: int, window: int = 16, margin: int = 2) -> State:
+    def run(self, n: int, window: int = 16, margin: int = 2, rounds_out: list | None = None) -> State:
         """n staggered steps with the solver's convergence read once per window of steps.
 
         Each step enqueues the explicit step and a fixed budget of CG rounds
@@ -401,7 +405,8 @@ class Simulator:
         solve did not finish within its budget, the window is rolled back to
         its first state and re-run with step(), which polls.  Rounds after a
         solve has finished do nothing, so the states equal those of step(n)
-        bit for bit.
+        bit for bit.  rounds_out, if given, receives each solve's CG round count
+        (the largest over the instances), in step order.
         """
         ni = self.mesh.n_instances
         if getattr(self, "_win_stats", None) is None or self._win_stats.shape[0] < window:
@@ -416,12 +421,14 @@ class Simulator:
                 self.step()
                 if self.solves_at(self.steps_done - 1):
                     its.append(max(s["iters"] for s in self.cg_stats()))
+                    if rounds_out is not None:
+                        rounds_out.append(its[-1])
             budget = (max(its) + margin) if its else 0
             done = k
         while done < n:
             w = min(window, n - done)
             if not budget:
-                self.step(w)
+                self.step(w, rounds_out)
                 its = [s["iters"] for s in self.cg_stats()]
                 budget = max(its) + margin if any(self.solves_at(self.steps_done - 1 - j) for j in range(w)) else 0
                 done += w
@@ -452,12 +459,14 @@ class Simulator:
                 self.state.copy_(snap[0])
                 self._next.d.copy_(snap[1])
                 self.active.copy_(snap[2])
-                self.step(w)
+                self.step(w, rounds_out)
                 budget = max(s["iters"] for s in self.cg_stats()) + 2 * margin
             else:
                 self.stats.copy_(self._win_stats[solved[-1]])
                 self.steps_done += w
                 budget = int(st[-8:, :, 0].max()) + margin
+                if rounds_out is not None:
+                    rounds_out.extend(int(r) for r in st[:, :, 0].max(axis=1))
             done += w
         self._budget = budget
         return self.state

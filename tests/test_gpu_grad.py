@@ -100,6 +100,33 @@ def test_checkpointing_does_not_change_the_gradient():
     assert out[0][0][0] == out[1][0][0] and out[0][1][0] == out[1][1][0]
 
 
+def test_recompute_enqueues_the_forward_round_counts():
+    """The reverse sweep recomputes each segment with exactly the CG rounds its solves took in the
+    forward sweep: no recomputed solve falls back to polling, and the gradient equals the one of a
+    recompute that enqueues a fixed budget and polls where it falls short."""
+    from paper_2606_23458_amd.grad import TrajectoryRunner
+    p = w.small_plate(32, 16, seed=7).with_(steps=30)
+    grads = []
+    for exact in (True, False):
+        sim = _sim(p, "f64")
+        run = TrajectoryRunner(sim, steps=30, checkpoint_every=8)
+        run.forward()
+        assert [len(r) for r in run.seg_rounds] == [8, 8, 8, 6]
+        assert all(r >= 2 for seg in run.seg_rounds for r in seg)
+        if not exact:
+            run.seg_rounds = [[] for _ in run.seg_rounds]
+            run._fwd_budget = 3   # too few rounds: the segment is redone with polling
+        calls = []
+        orig = sim.step_into
+        sim.step_into = lambda *a, **k: (calls.append(1), orig(*a, **k))[1]
+        dbar = (sim.state.d * 1e-2).contiguous()
+        grads.append(run.backward(dbar).cpu().numpy())
+        sim.step_into = orig
+        # the budget of 3 rounds fails at least the first segment processed (the last 6 steps)
+        assert (len(calls) == 0) if exact else (len(calls) >= 6)
+    assert grads[0][0] == grads[1][0]
+
+
 def test_fp32_gradient_close_to_oracle():
     from paper_2606_23458_amd.grad import loss_and_grad
     p = w.small_plate(32, 16, jitter=0.05, seed=7).with_(steps=40)
