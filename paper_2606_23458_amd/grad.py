@@ -47,6 +47,11 @@ class TrajectoryRunner:
                            for _ in range(self.K + 1)]
         self.adj = [State(mesh), State(mesh)]
         self.checkpoints: list[State] = []
+        # steps per convergence read of the forward sweep (Simulator.run): a
+        # solve that outruns the window's round budget (the round count jumps
+        # when the crack starts to move) sends the window back to polled
+        # stepping, so short windows keep that redo short
+        self.window = 8
 
     def forward(self) -> State:
         """Run all steps from the simulator's initial state; keep checkpoints (state + held flags)."""
@@ -61,7 +66,7 @@ class TrajectoryRunner:
         for n0 in range(0, self.steps, self.K):
             k = min(self.K, self.steps - n0)
             rounds: list[int] = []
-            sim.run(k, window=min(k, 25), rounds_out=rounds)
+            sim.run(k, window=min(k, self.window), rounds_out=rounds)
             self.seg_rounds.append(rounds if len(rounds) == k else [])
             if n0 + k < self.steps:
                 self.checkpoints.append((sim.state.clone(), sim.active.clone(), sim._next.d.clone()))

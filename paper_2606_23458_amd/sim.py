@@ -298,6 +298,7 @@ class Simulator:
         self.cg = cg or CgConfig(tol=default_tol(self.dtype_code))
         # adjoint solves stop relative to their right-hand side
         self.cg_adj = cg_adj or CgConfig(tol=default_tol(self.dtype_code))
+        self.window_redos = 0   # windows of run() re-run with polling (a solve outran its budget)
         self.stats = torch.zeros(n * 6, dtype=torch.int32, device=self.mesh.device)   # pf_cg_stats_t[n]
         self.active = self.initial_active()
         self._active_next = torch.zeros_like(self.active)
@@ -455,6 +456,7 @@ class Simulator:
                 self.steps_done += w
             elif np.any(st[:, :, 3] != 0):
                 # a solve did not finish within the budget: redo the window, polling
+                self.window_redos += 1
                 self.state, self._next, self.active, self._active_next = refs
                 self.state.copy_(snap[0])
                 self._next.d.copy_(snap[1])
