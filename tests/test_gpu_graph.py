@@ -8,10 +8,11 @@ import workloads as w
 pytestmark = pytest.mark.gpu
 
 
-def _pair(probs, dtype, rounds, more, steps):
-    from paper_2606_23458_amd import GraphStepper, Simulator
-    eager = Simulator(probs, dtype=dtype)
-    graph = Simulator(probs, dtype=dtype, dt=list(eager.dt))
+def _pair(probs, dtype, rounds, more, steps, damage_chunks=0):
+    from paper_2606_23458_amd import GraphStepper, Mesh, Simulator
+    mesh = (lambda: Mesh(probs, dtype, 256, damage_chunks=damage_chunks)) if damage_chunks else (lambda: None)
+    eager = Simulator(probs, dtype=dtype, mesh=mesh())
+    graph = Simulator(probs, dtype=dtype, dt=list(eager.dt), mesh=mesh())
     gs = GraphStepper(graph, rounds=rounds, more=more)   # takes one eager step
     eager.step()
     for k in range(steps):
@@ -37,6 +38,12 @@ def test_graph_continuation_rounds_equal_eager():
     """Tiny first graphs force several resumed continuations per step."""
     gs = _pair([w.small_plate(32, 16, seed=3)], "f64", rounds=3, more=2, steps=8)
     assert gs.continuations > 8
+
+
+def test_graph_two_element_chunks_equal_eager():
+    """Graph-replayed rounds and resumed continuations with the damage passes in two element chunks."""
+    gs = _pair([w.small_plate(40, 20, seed=6)], "f64", rounds=5, more=3, steps=6, damage_chunks=2)
+    assert gs.sim.mesh.damage_chunks == 2 and gs.continuations > 4
 
 
 def test_graph_batched_fp32():
