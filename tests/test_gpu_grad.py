@@ -100,6 +100,24 @@ def test_checkpointing_does_not_change_the_gradient():
     assert out[0][0][0] == out[1][0][0] and out[0][1][0] == out[1][1][0]
 
 
+def test_gradient_independent_of_damage_element_chunks():
+    """The reverse sweep (adjoint linear solves included) gives the same bits with the damage
+    passes' elements in one or two chunks."""
+    from paper_2606_23458_amd import Mesh, Simulator
+    from paper_2606_23458_amd.grad import loss_and_grad
+    p = w.small_plate(40, 20, seed=8).with_(steps=16)
+    osim = OSim(p)
+    target = orun(p, steps=16, Gc=3.0, sim=osim)[0].d.numpy()
+    out = []
+    for nch in (1, 2):
+        mesh = Mesh([p], "f64", 256, damage_chunks=nch)
+        assert mesh.damage_chunks == nch
+        sim = Simulator(p, dtype="f64", mesh=mesh, dt=[osim.dt])
+        tgt = torch.tensor(sim.mesh.nodes_to_internal([target]), dtype=torch.float64, device="cuda")
+        out.append(loss_and_grad(sim, [2.0], tgt, steps=16, checkpoint_every=5))
+    assert out[0][0][0] == out[1][0][0] and out[0][1][0] == out[1][1][0]
+
+
 def test_recompute_enqueues_the_forward_round_counts():
     """The reverse sweep recomputes each segment with exactly the CG rounds its solves took in the
     forward sweep: no recomputed solve falls back to polling, and the gradient equals the one of a
