@@ -70,7 +70,7 @@ BYTES_BASIS = {
     0: "explicit step, paper layout: nodes 14w+4 B (u, v, a read and written, 1/m, d, CSR row pointer) "
        "at N = N_e/2, elements 24+9w B (int32 connectivity, 6 grad phi + area, H read and written, "
        "3 int32 corner ids)",
-    1: "damage CG iterate pass, this build's arrays costed with 32-bit indices: nodes 11w+1 B (r, Az, Ap, p, "
+    1: "damage CG iterate pass, the library's arrays costed with 32-bit indices: nodes 11w+1 B (r, Az, Ap, p, "
        "x, 1/diag and the held flag read; p, Ap, x, r, Az written) at N = N_e/2, elements 4w+24 B "
        "(3 stiffness off-diagonals, the mass coefficient, connectivity, corner ids); intermediates "
        "kept in LDS are not counted",
@@ -695,7 +695,7 @@ def main():
                     help="also copy a 256 MiB device buffer 3 times (known traffic, for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the sharded layout is a "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (the sharded layout is a "
                                    "design only)"}))
         sys.exit(2)
     tile = args.tile_nodes
