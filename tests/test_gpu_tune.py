@@ -90,3 +90,18 @@ def test_damage_element_chunks_agree_bitwise(dtype, tile, precond, monotone):
         assert a.cg_stats()[0]["iters"] == b.cg_stats()[0]["iters"]
     torch.cuda.synchronize()
     assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
+
+
+def test_damage_element_chunks_agree_bitwise_batched():
+    """A batched handle of two plates of different sizes (fused rounds per instance): one or two
+    damage element chunks give the same bits."""
+    from paper_2606_23458_amd import Mesh, Simulator
+    probs = [w.small_plate(64, 32, seed=3), w.small_plate(30, 14, seed=9, model=1)]
+    ma = Mesh(probs, "f32", 256, damage_chunks=1)
+    mb = Mesh(probs, "f32", 256, damage_chunks=2)
+    a = Simulator(probs, dtype="f32", mesh=ma)
+    b = Simulator(probs, dtype="f32", mesh=mb, dt=list(a.dt))
+    a.step(10)
+    b.step(10)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state.nodes, b.state.nodes) and torch.equal(a.state.H, b.state.H)
