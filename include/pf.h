@@ -287,8 +287,9 @@ pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const void* H, co
  * restricted to the free nodes (Sec. 4.2), the Gc term
  * -(l0 lambda'K d + lambda'M d / l0) for AT2 (eq. implicit_gc_l0_element_term)
  * and its AT1 counterpart; nodes held at d_prev pass their adjoint to d_prev,
- * nodes held at 1 pass none.  The adjoint CG warm-starts from the previous
- * call's multiplier held by the handle.  Projected bounds only.
+ * nodes held at 1 pass none.  The adjoint CG warm-starts from the linear
+ * extrapolation of the previous two calls' multipliers held by the handle
+ * (from the previous one on the second call).  Projected bounds only.
  * adj_np1 is read only; adj_n must not alias adj_np1, s_n or s_np1.
  */
 pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt,

@@ -23,7 +23,8 @@ namespace pf {
 // previous lambda (zero on held nodes).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* __restrict__ act,
-                                                     const T* __restrict__ dbar, T* b, uint8_t* W, T* lam) {
+                                                     const T* __restrict__ dbar, T* b, uint8_t* W, T* lam,
+                                                     T* lam_prev, int extrap) {
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
   for (int i = threadIdx.x; i < t.n_own; i += kBlock) {
@@ -33,7 +34,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* 
     const uint8_t w = (a & PF_ACTIVE_LOWER) ? 1 : ((a & PF_ACTIVE_UPPER) ? 2 : 0);
     W[g] = w;
     b[g] = w ? T(0) : dbar[g];
-    if (w) lam[g] = T(0);
+    // start from the linear extrapolation of the last two multipliers (the
+    // multiplier changes smoothly from step to step), else from the last
+    const T l = lam[g];
+    lam[g] = w ? T(0) : (extrap ? T(2) * l - lam_prev[g] : l);
+    lam_prev[g] = l;
   }
 }
 
@@ -319,7 +324,9 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   T* lam = static_cast<T*>(m->dw.lam);
   timer_begin(m, 3, s);
   hipLaunchKernelGGL(k_adj_prep<T>, grid, block, 0, s, m->dm, act, static_cast<const T*>(adj1->d),
-                     static_cast<T*>(m->dw.b), m->dw.wset, lam);
+                     static_cast<T*>(m->dw.b), m->dw.wset, lam, static_cast<T*>(m->dw.lam_prev),
+                     m->adj_calls >= 2 ? 1 : 0);
+  m->adj_calls += 1;
   timer_end(m, 3, s);
   PF_HIP(hipGetLastError());
   pf_cg_opts_t oa = *o;

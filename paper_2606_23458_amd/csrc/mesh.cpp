@@ -619,7 +619,7 @@ extern "C" pf_status_t pf_mesh_create(const pf_mesh_desc_t* inst, int32_t n_inst
   const size_t nb = size_t(m->n_nodes) * w;
   void** vecs[] = {&m->dw.b,  &m->dw.dinv, &m->dw.r0, &m->dw.r1,  &m->dw.w0,  &m->dw.w1,
                    &m->dw.s0, &m->dw.s1,   &m->dw.p,  &m->dw.xw0, &m->dw.xw1, &m->dw.lam,
-                   &m->dw.zb, &m->dw.y0,   &m->dw.y1, &m->dw.dv};
+                   &m->dw.lam_prev, &m->dw.zb, &m->dw.y0, &m->dw.y1, &m->dw.dv};
   for (void** v : vecs)
     if ((st = dev_alloc(m, nb, v)) != PF_OK) { free_all(m); delete m; return st; }
   void* tmpp;

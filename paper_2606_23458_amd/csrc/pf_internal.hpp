@@ -132,6 +132,7 @@ struct DevWork {
   void* dv;                          // [n_nodes] Chebyshev update direction (polynomial preconditioner)
   uint8_t* wset;                     // [2][n_nodes] held-set pair
   void* lam;                         // [n_nodes] adjoint multiplier (warm start of the next adjoint solve)
+  void* lam_prev;                    // [n_nodes] the multiplier of the call before (linear extrapolation)
   void* hbar;                        // [n_elems] adjoint of H_{n+1} (adjoint step scratch)
   void* mte;                         // [n_te] per-solve mass coefficient (c0 + cH H_e) A_e / 12 of each tile element
   double* part;                      // [n_tiles][8] block partials
@@ -160,6 +161,7 @@ struct pf_mesh_s {
   size_t adj_lds_damage = 0;         // LDS of the adjoint kernels (set by the first backward step)
   size_t adj_lds_explicit = 0;
   int32_t adj_chunks = 0;            // element chunks of the explicit step's adjoint (0: not yet chosen)
+  int64_t adj_calls = 0;             // pf_step_backward calls on this handle
   int32_t explicit_block = 256;      // workgroup size of the explicit-step kernel (256 or 512)
   int32_t max_lds_explicit2 = 0;     // LDS of the explicit step with its elements in two chunks
   int32_t explicit_chunks = 0;       // 1, 2, or 0 = automatic
