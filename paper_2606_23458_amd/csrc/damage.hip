@@ -185,12 +185,13 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   __shared__ double red[8 * 4 * kWaves];
   const int tile = tile_of_block(a.dm.n_tiles);
   const TileRec t = a.dm.tiles[tile];
-  // the corner lists do not depend on the solver state: their loads go first
-  StagedCorners<2, 12> scn;   // 256 threads: 512 offsets, 3072 corner ids in registers
-  stage_corners_load(a.dm, t, scn);
   const Ctl* c = a.ctl + t.inst;
   const int mode = c->mode;
   if (mode == MODE_DONE) return;
+  // the corner lists do not depend on the solver state: their loads go
+  // first, once a finished solve's pass has left
+  StagedCorners<2, 12> scn;   // 256 threads: 512 offsets, 3072 corner ids in registers
+  stage_corners_load(a.dm, t, scn);
   // Chebyshev steps and the A z pass follow the main pass of first / iterate rounds only
   const int stage = CHEB ? a.stage : 0;
   if (CHEB && stage > 0 && (mode == MODE_RESTART || mode == MODE_CHECK)) return;
