@@ -24,7 +24,7 @@ instead).  The same steps are timed with windowed and with polled stepping
                 the large plates);
   fp32          the same headline in FP32 kernels (FP64 CG reductions);
   perforated    the 1448x724 perforated plate (AT1 / star-convex / plane
-                stress, FP32);
+                stress, FP32; the same steps in FP64 under 'f64');
   batched_step  one explicit step and one staggered step of all 64 plates
                 (FP32, 6.8M triangles, beyond the Infinity Cache);
   bwd_fwd       backward/forward time of the checkpointed gradient on the
@@ -359,21 +359,32 @@ def fp32_companion(steps: int, warmup: int, tile_nodes) -> dict:
 
 def perforated(steps: int = 60, warmup: int = 20) -> dict:
     """The perforated plate (2.09M triangles, random diagonals, six holes; AT1 / star-convex / plane
-    stress, FP32 as configured): staggered steps and the explicit step alone."""
+    stress, FP32 as configured): staggered steps and the explicit step alone; the same steps again
+    in FP64 (the paper's arithmetic) under 'f64'."""
     import workloads as w
-    p = w.config2()
-    sim = plate_simulator(p, DEFAULT_TILE["f32"], "f32")
-    ne = sim.mesh.n_elems
-    sim.run(warmup)
-    ms = timed_run(sim, steps)
-    it = []
-    for _ in range(10):
-        sim.step()
-        it.append(sim.cg_stats()[0]["iters"])
-    return {"workload": f"1448x724 perforated plate, {ne} triangles, {sim.mesh.n_nodes} nodes, AT1 / star-convex / "
-                        f"plane stress, FP32, steps {warmup + 1}-{warmup + steps}",
-            "elem_steps_per_s": round(ne / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
-            "cg_iters_per_solve": round(sum(it) / len(it), 2), "explicit_step": explicit_only(sim, 40, 4)}
+
+    def one(dtype: str) -> dict:
+        p = w.config2().with_(dtype=dtype)
+        sim = plate_simulator(p, DEFAULT_TILE[dtype], dtype)
+        ne = sim.mesh.n_elems
+        sim.run(warmup)
+        ms = timed_run(sim, steps)
+        it = []
+        for _ in range(10):
+            sim.step()
+            it.append(sim.cg_stats()[0]["iters"])
+        return {"workload": f"1448x724 perforated plate, {ne} triangles, {sim.mesh.n_nodes} nodes, AT1 / "
+                            f"star-convex / plane stress, {dtype.upper()}, steps {warmup + 1}-{warmup + steps}",
+                "elem_steps_per_s": round(ne / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+                "cg_iters_per_solve": round(sum(it) / len(it), 2),
+                "explicit_step": explicit_only(sim, 40, WIDTH[dtype]),
+                "tile_plan": {"tile_nodes": sim.mesh.tile_nodes, "damage_chunks": sim.mesh.damage_chunks,
+                              "n_tiles": int(sim.mesh.totals.n_tiles)}}
+
+    out = one("f32")
+    gpu_sync()
+    out["f64"] = one("f64")
+    return out
 
 
 def batched_step(steps: int = 30) -> dict:
