@@ -18,7 +18,10 @@
 // (With a release threshold near tol, where the solution's tail varies on the
 // scale of tol, each release pushes the next ring of held nodes just over the
 // threshold and the held set shrinks one ring per check; well below tol the
-// whole tail is released at once.)
+// whole tail is released at once.)  A restart pass sees the state a check
+// would see and counts the changes that check would make: a restart whose
+// free residual passes with none to make ends the solve (a damage field that
+// does not move, e.g. AT1 below its threshold, takes one round).
 // Each check is one primal-dual active-set update; if eight updates have not
 // settled the set, the solve switches to a monotone projected CG: steps are
 // cut at the first bound and followed by a projected Jacobi-gradient step of
@@ -539,6 +542,14 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
           const bool want_up = ri > T(0) || (wold == HELD_UPPER && !(release && sr < -kRelease * tol));
           w = (xv <= lbv && want_lo) ? HELD_LOWER : ((xv >= T(1) && want_up) ? HELD_UPPER : HELD_NONE);
         }
+        if (mode == MODE_RESTART && !monotone && w != HELD_FIXED) {
+          // what a check pass of this state would change: it would see the
+          // same x, held set and residual, so a restart whose free residual
+          // passes and which counts nothing here ends the solve itself
+          const bool viol = w == HELD_NONE && (double(lbv) - double(xv) > tol || double(xv) - 1.0 > tol);
+          const bool rel = (w == HELD_LOWER && sr > kRelease * tol) || (w == HELD_UPPER && sr < -kRelease * tol);
+          ch += (viol || rel) ? 1.0 : 0.0;
+        }
       }
       xn_[g] = xv;
       rn_[g] = ri;
@@ -761,7 +772,8 @@ __device__ __forceinline__ void advance_solver(Ctl* c, const double (&v)[8], int
         c->mode = MODE_FIRST;
       }
     } else if (scf <= tl) {
-      c->mode = projected ? MODE_CHECK : MODE_DONE;
+      // a restart counts the changes a check of its state would make
+      c->mode = (projected && sch > 0.0) ? MODE_CHECK : MODE_DONE;
     } else {
       c->mode = MODE_FIRST;
     }

@@ -95,7 +95,9 @@ def test_in_pass_combination_equals_reduction_launch_bitwise(dtype):
     assert both.cg_stats()[0]["iters"] == one.cg_stats()[0]["iters"]
 
 
-def _solve(p, dtype, H, lb):
+def _solve(p, dtype, H, lb, again=False):
+    """One damage solve from d_prev = lb; again: then a second solve from its result, seeded
+    with its held set (as the next step of a trajectory whose damage did not move)."""
     from paper_2606_23458_amd import Simulator, State
     sim = Simulator(p, dtype=dtype, tile_nodes=64)
     st = {"u": np.zeros((p.n_nodes, 2)), "v": np.zeros((p.n_nodes, 2)), "a": np.zeros((p.n_nodes, 2)),
@@ -103,6 +105,11 @@ def _solve(p, dtype, H, lb):
     s_in = State.from_user(sim.mesh, [st])
     d_out = torch.zeros_like(s_in.d)
     sim.damage(s_in.H, s_in.d, d_out, sim.active)
+    if again:
+        d2 = torch.zeros_like(d_out)
+        flags = sim.active.clone()
+        sim.damage(s_in.H, d_out, d2, sim.active, guess=flags)
+        d_out = d2
     torch.cuda.synchronize()
     return sim.mesh.nodes_from_internal(d_out.double())[0], sim.cg_stats()[0]
 
@@ -114,6 +121,7 @@ def test_every_node_fixed(dtype):
     H = np.random.default_rng(1).uniform(0, 5000, p.n_elems)
     d, st = _solve(p, dtype, H, np.ones(p.n_nodes))
     assert np.all(d == 1.0) and st["flags"] == 0
+    assert st["iters"] == 1   # no free node: the restart's residual passes and nothing can change
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -127,3 +135,7 @@ def test_at1_below_threshold_stays_at_the_bound(dtype):
     ref = DamageQP(OSim(p).mesh, p.l0, 1).solve(H, p.Gc, np.zeros(p.n_nodes))[0]
     assert np.all(ref == 0.0)
     assert np.all(d == 0.0) and st["flags"] == 0
+    # the next solve, seeded with this held set, ends in its restart round: every node held
+    # at the bound with its residual pointing outward, so a check would change nothing
+    d2, st2 = _solve(p, dtype, H, np.zeros(p.n_nodes), again=True)
+    assert np.all(d2 == 0.0) and st2["flags"] == 0 and st2["iters"] == 1, st2

@@ -130,7 +130,7 @@ def test_recompute_enqueues_the_forward_round_counts():
         run = TrajectoryRunner(sim, steps=30, checkpoint_every=8)
         run.forward()
         assert [len(r) for r in run.seg_rounds] == [8, 8, 8, 6]
-        assert all(r >= 2 for seg in run.seg_rounds for r in seg)
+        assert all(r >= 1 for seg in run.seg_rounds for r in seg)
         if not exact:
             run.seg_rounds = [[] for _ in run.seg_rounds]
             run._fwd_budget = 3   # too few rounds: the segment is redone with polling
