@@ -143,6 +143,47 @@ def test_fp64_headline_configuration_matches_oracle():
         assert max(errs.values()) < 1e-9, (k, errs)
 
 
+def test_fp64_perforated_configuration_matches_oracle():
+    """The perforated plate (AT1, star-convex, plane stress, irregular node valence) in FP64 as
+    bench.py times it (448-node tiles): one explicit step from a random state element by element,
+    then, after 450 GPU steps, three staggered steps of the GPU and the oracle from the same state,
+    to the FP64 bar (damage 1e-9 at every node, mechanics 1e-9 relative)."""
+    from paper_2606_23458_amd import Simulator, State
+    from tests.gpu_common import random_state, to_oracle
+    p = w.config2().with_(dtype="f64")
+    osim0 = OSim(p)
+    sim = Simulator(p, dtype="f64", tile_nodes=448, dt=[osim0.dt])
+    st = random_state(p, seed=41)
+    s_in = State.from_user(sim.mesh, [st])
+    s_out = State(sim.mesh)
+    sim.explicit(s_in, s_out)
+    torch.cuda.synchronize()
+    got = s_out.to_user()[0]
+    u1, v1, a1, H1, _ = osim0.explicit(to_oracle(st))
+    for f, ref in (("u", u1), ("v", v1), ("a", a1), ("H", H1)):
+        assert rel_err(got[f], ref.numpy()) < 1e-12, f
+    del osim0
+    sim.reset()
+    sim.run(450)
+    torch.cuda.synchronize()
+    start = sim.state.to_user()[0]
+    assert np.sum((start["d"] > 1e-3) & (start["d"] < 1.0)) > 100
+    osim = OSim(p, dt=sim.dt[0], qp_inner="cg")
+    f = lambda x: torch.as_tensor(np.asarray(x, dtype=np.float64)).clone()
+    ost = OState(f(start["u"]), f(start["v"]), f(start["a"]), f(start["d"]), f(start["H"]))
+    for k in range(3):
+        sim.step()
+        ost = osim.step(ost)
+        torch.cuda.synchronize()
+        got = sim.state.to_user()[0]
+        assert sim.cg_stats()[0]["flags"] == 0
+        dd = float(np.max(np.abs(got["d"] - ost.d.numpy())))
+        errs = {fld: rel_err(got[fld], getattr(ost, fld).numpy()) for fld in ("u", "v", "a", "H")}
+        print(f"perforated FP64 step {451 + k}: max|d - d_oracle| {dd:.2e}, rel {errs}", flush=True)
+        assert dd <= 1e-9, (k, dd)
+        assert max(errs.values()) < 1e-9, (k, errs)
+
+
 def test_batched_fp32_backward_equals_single_instances():
     """The 64-plate workload's physics (FP32, 300 steps, checkpoints every 50): the reverse sweep of a
     batched handle gives each instance the dL/dGc of its single-instance handle, bit for bit."""
