@@ -700,8 +700,9 @@ def main():
                     help="comma-separated extra sections to run (default: all; names as on the JSON line), "
                          "e.g. bwd_fwd,batched to profile the backward")
     ap.add_argument("--skip-headline", action="store_true",
-                    help="profiling aid: run only the --sections (batched_bwd: the batched forward+backward "
-                         "without the one-plate-at-a-time loop) and print their results")
+                    help="profiling aid: run only the --sections bwd_fwd, batched, batched_bwd (the batched "
+                         "forward+backward without the one-plate-at-a-time loop) or perforated, and print their "
+                         "results")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also copy a 256 MiB device buffer 3 times (known traffic, for counter calibration)")
     args = ap.parse_args()
@@ -727,7 +728,7 @@ def main():
         del a, c
     if args.skip_headline:
         extra = {"bwd_fwd": bwd_fwd_ratio, "batched": batched_vs_plain,
-                 "batched_bwd": lambda: batched_vs_plain(plain=False)}
+                 "batched_bwd": lambda: batched_vs_plain(plain=False), "perforated": perforated}
         out = {k: extra[k]() for k in (args.sections or "").split(",") if k in extra}
         print(json.dumps(out))
         return
