@@ -141,11 +141,15 @@ typedef struct {
                                 default path); 1: after every round;
                                 0: enqueue exactly max_iter rounds and never
                                 synchronise (suitable for HIP-graph capture) */
-    int32_t start;           /* damage solve only.  0: start from d_prev;
+    int32_t start;           /* damage solve: 0: start from d_prev;
                                 1: start from clamp(2 d_prev - d, d_prev, 1),
                                 where the output array d holds, on entry, the
                                 damage of the step before d_prev (a linear
-                                extrapolation in time) */
+                                extrapolation in time).  pf_step_backward:
+                                1: warm start from the multipliers of the
+                                handle's previous calls; 0: start from zero and
+                                forget them (the first call of a reverse sweep,
+                                so that a sweep repeats a fresh handle's bits) */
     int32_t monotone;        /* damage solve only.  1: use the monotone
                                 projected CG from the start instead of
                                 held-set updates between CG runs (slower; the
@@ -289,7 +293,9 @@ pf_status_t pf_damage_solve(pf_mesh_t m, const pf_params_t* p, const void* H, co
  * and its AT1 counterpart; nodes held at d_prev pass their adjoint to d_prev,
  * nodes held at 1 pass none.  The adjoint CG warm-starts from the linear
  * extrapolation of the previous two calls' multipliers held by the handle
- * (from the previous one on the second call).  Projected bounds only.
+ * (from the previous one on the second call); opts->start = 0 starts it from
+ * zero and counts calls afresh (a fresh handle's first call starts from zero
+ * too).  Projected bounds only.
  * adj_np1 is read only; adj_n must not alias adj_np1, s_n or s_np1.
  */
 pf_status_t pf_step_backward(pf_mesh_t m, const pf_params_t* p, const double* dt,

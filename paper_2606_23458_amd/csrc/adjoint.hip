@@ -20,11 +20,11 @@
 namespace pf {
 
 // Right-hand side and working set of the adjoint solve; warm start from the
-// previous lambda (zero on held nodes).
+// previous lambda, or from zero when cold (zero on held nodes).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* __restrict__ act,
                                                      const T* __restrict__ dbar, T* b, uint8_t* W, T* lam,
-                                                     T* lam_prev, int extrap) {
+                                                     T* lam_prev, int extrap, int cold) {
   const int tile = tile_of_block(dm.n_tiles);
   const TileRec t = dm.tiles[tile];
   for (int i = threadIdx.x; i < t.n_own; i += kBlock) {
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(DevMesh dm, const uint8_t* 
     // start from the linear extrapolation of the last two multipliers (the
     // multiplier changes smoothly from step to step), else from the last
     const T l = lam[g];
-    lam[g] = w ? T(0) : (extrap ? T(2) * l - lam_prev[g] : l);
+    lam[g] = (w || cold) ? T(0) : (extrap ? T(2) * l - lam_prev[g] : l);
     lam_prev[g] = l;
   }
 }
@@ -322,10 +322,14 @@ static pf_status_t backward_t(pf_mesh_s* m, int split, const pf_state_t* s_n, co
   const dim3 grid(m->n_tiles), block(kBlock);
   const InstP<T>* ip = static_cast<const InstP<T>*>(m->dw.instp);
   T* lam = static_cast<T*>(m->dw.lam);
+  // start = 0: a cold start that forgets the multipliers of the handle's
+  // previous calls (a reverse sweep that begins so repeats a fresh handle's bits)
+  const bool cold = o->start == 0;
+  if (cold) m->adj_calls = 0;
   timer_begin(m, 3, s);
   hipLaunchKernelGGL(k_adj_prep<T>, grid, block, 0, s, m->dm, act, static_cast<const T*>(adj1->d),
                      static_cast<T*>(m->dw.b), m->dw.wset, lam, static_cast<T*>(m->dw.lam_prev),
-                     m->adj_calls >= 2 ? 1 : 0);
+                     m->adj_calls >= 2 ? 1 : 0, cold ? 1 : 0);
   m->adj_calls += 1;
   timer_end(m, 3, s);
   PF_HIP(hipGetLastError());

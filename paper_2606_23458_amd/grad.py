@@ -11,6 +11,7 @@ its conclusions).
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import time
 
 import numpy as np
@@ -106,6 +107,7 @@ class TrajectoryRunner:
         cur.zero_()
         cur.nodes[6].copy_(d_bar)
         n_seg = len(self.checkpoints)
+        self._cold = True
         for sgi in range(n_seg - 1, -1, -1):
             k0 = sgi * self.K
             k1 = min(k0 + self.K, self.steps)
@@ -162,11 +164,14 @@ class TrajectoryRunner:
             self._fwd_budget = int(st[:, :, 0].max()) + 4
 
     def _reverse(self, n: int, cur: State, nxt: State, dGc: torch.Tensor):
-        # the adjoint solves warm-start from the previous step's multiplier, so
-        # they run polled, in order, and are never redone
+        # the adjoint solves warm-start from the previous steps' multipliers, so
+        # they run polled, in order, and are never redone; the sweep's first
+        # solve starts cold, so a sweep gives the same bits on a reused handle
         sim, states, act = self.sim, self.seg_states, self.seg_active
         for j in range(n - 1, -1, -1):
-            backward_step(sim, states[j], states[j + 1], act[j + 1], cur, nxt, dGc)
+            cg = dataclasses.replace(sim.cg_adj, start=0) if self._cold else None
+            self._cold = False
+            backward_step(sim, states[j], states[j + 1], act[j + 1], cur, nxt, dGc, cg=cg)
             cur, nxt = nxt, cur
         return cur, nxt
 

@@ -118,6 +118,29 @@ def test_gradient_independent_of_damage_element_chunks():
     assert out[0][0][0] == out[1][0][0] and out[0][1][0] == out[1][1][0]
 
 
+def test_gradient_repeats_bitwise_on_a_reused_handle():
+    """A reverse sweep starts its first adjoint solve cold (the later ones warm-start from the
+    sweep's own multipliers), so the gradient of a trajectory evaluated again on the same handle,
+    after a sweep with another adjoint seed, has the bits of the first evaluation and of a fresh
+    handle."""
+    from paper_2606_23458_amd.grad import TrajectoryRunner
+    p = w.small_plate(32, 16, seed=7).with_(steps=24)
+    grads = []
+    sim = _sim(p, "f64")
+    run = TrajectoryRunner(sim, steps=24, checkpoint_every=8)
+    run.forward()
+    dbar = (sim.state.d * 1e-2).contiguous()
+    grads.append(run.backward(dbar).cpu().numpy())
+    other = run.backward((dbar * 3.0 + 1e-3).contiguous()).cpu().numpy()
+    grads.append(run.backward(dbar).cpu().numpy())
+    fresh = _sim(p, "f64")
+    rf = TrajectoryRunner(fresh, steps=24, checkpoint_every=8)
+    rf.forward()
+    grads.append(rf.backward((fresh.state.d * 1e-2).contiguous()).cpu().numpy())
+    assert grads[0][0] != 0.0 and other[0] != grads[0][0]
+    assert grads[0][0] == grads[1][0] == grads[2][0], grads
+
+
 def test_recompute_enqueues_the_forward_round_counts():
     """The reverse sweep recomputes each segment with exactly the CG rounds its solves took in the
     forward sweep: no recomputed solve falls back to polling, and the gradient equals the one of a
