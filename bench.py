@@ -22,6 +22,8 @@ instead).  The same steps are timed with windowed and with polled stepping
                 perforated plate and four plates of the 64-plate workload
                 (--cpu-protocol full: 20-step windows after 5 warm-up steps on
                 the large plates);
+  damage_cg     the damage CG in element-iterations per second, over the
+                whole solve and for the iterate pass alone;
   fp32          the same headline in FP32 kernels (FP64 CG reductions);
   perforated    the 1448x724 perforated plate (AT1 / star-convex / plane
                 stress, FP32; the same steps in FP64 under 'f64');
@@ -333,6 +335,20 @@ def roofline(res) -> dict:
     return out
 
 
+def damage_cg_rates(res, hb: dict, explicit_us: float, pass_us: float) -> dict:
+    """Damage CG throughput in element-iterations per second (one iteration = one round: a pass
+    over the plate and its reduction): over the whole solve (rounds per step over the step time
+    less the explicit step alone), and for the iterate pass alone (back to back)."""
+    ne = res["ne"]
+    rounds = hb["cg_iters_per_solve"]["mean"]
+    solve_s = (hb["ms_per_step"] - explicit_us / 1e3) / 1e3
+    return {"elem_iterations_per_s": round(ne * rounds / solve_s, 1),
+            "pass_elem_iterations_per_s": round(ne / (pass_us / 1e6), 1),
+            "rounds_per_solve": rounds, "us_per_round": round(solve_s / rounds * 1e6, 2),
+            "basis": "rounds per solve x elements / (step time - explicit step alone); the pass alone: "
+                     "elements / back-to-back iterate pass time"}
+
+
 def headline_block(res, steps: int) -> dict:
     """value, time per step and CG counts of a run_headline result."""
     ne = res["ne"]
@@ -353,6 +369,7 @@ def fp32_companion(steps: int, warmup: int, tile_nodes) -> dict:
     rf = roofline(res)
     out["roofline"] = {k: rf[k] for k in ("kernel", "achieved", "frac", "traffic", "measured_GBps",
                                           "avg_launch_us", "alg_bytes_per_launch", "in_solve_events_us")}
+    out["damage_cg"] = damage_cg_rates(res, out, out["explicit_step"]["us_per_step"], rf["avg_launch_us"])
     out["tile_nodes"] = res["sim"].mesh.tile_nodes
     return out
 
@@ -763,6 +780,8 @@ def main():
     }
     res["b2b_s"] = damage_pass_b2b(sim)
     out["roofline"] = roofline(res)
+    out["damage_cg"] = damage_cg_rates(res, out, out["explicit_step"]["us_per_step"],
+                                       out["roofline"]["avg_launch_us"])
     cp = copy_bandwidth()
     out["roofline"]["copy_kernel_GBps"] = cp["GBps"]
     out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / cp["GBps"], 4)
