@@ -230,16 +230,14 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   // after sv (8-byte aligned): iteration passes keep the element corner values
   // of A^e z^e in T; restart and check passes keep them in FP64 (the true
   // residual is then accurate to the rounding of x, not of an FP32 matvec) a
-  // chunk of elements at a time; the set-up sweep uses the same space for
-  // diagonal corners and loads
+  // chunk of elements at a time; the set-up sweep keeps those FP64 values
+  // beside its diagonal corners and loads
   uint16_t* coffs = reinterpret_cast<uint16_t*>(sv + nloc);   // [n_own + 1] corner-list offsets
   uint16_t* clist = coffs + t.n_own + 1;                     // [n_corner] corner ids
   unsigned char* rest =
       smem + ((size_t(nloc) * sizeof(T) + 2 * (size_t(t.n_own) + 1 + size_t(t.n_corner)) + 7) & ~size_t(7));
   T* qc = reinterpret_cast<T*>(rest);          // [3 n_telem] (first, iterate)
   double* qd = reinterpret_cast<double*>(rest); // [3 chunk]   (restart, check)
-  T* dc = reinterpret_cast<T*>(rest);          // [3 chunk]   diagonal corners (set-up)
-  T* bc = dc;                                  // [chunk] from offset 3 chunk: load per corner (set-up)
   const int tid = threadIdx.x;
 
 
@@ -391,18 +389,30 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   // three values per element instead of the six gradients and the area:
   //   (A^e z)_k = kap phi_e sum_{l != k} K_kl (z_l - z_k) + mA (z_k + z_0 + z_1 + z_2)
   const T* __restrict__ kw = static_cast<const T*>(a.dm.kw);
+  // restart / check: FP64 sums of each owned node's corner values of A x
+  constexpr bool kFusedSetup = sizeof(T) == 8;   // the set-up sweep sums them too
+  double qacc[NPT];
+  // set-up: b and D^-1 of the owned nodes, kept for the true residual
+  T bset[NPT], dset[NPT];
   if (setup) {
     T dacc[NPT], bacc[NPT], sacc[NPT];
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) dacc[r] = T(0), bacc[r] = T(0), sacc[r] = T(0);
-    // 2 nch chunks: 4 values of width w per element fit the 3 / nch values per
-    // element of the corner space (chunks split each node's corner sequence
-    // without reordering it, so the sums do not depend on the chunking).  The
-    // Chebyshev preconditioner also needs the absolute row sums of the element
-    // matrices (7 values per element): 4 nch chunks.
-    const int nsc = (CHEB ? 4 : 2) * NCH;
-    const int chs = (t.n_telem + nsc - 1) / nsc;
-    T* sc_ = dc + 4 * chs;   // [3 chunk] absolute row sums per corner (Chebyshev)
+    for (int r = 0; r < NPT; ++r) dacc[r] = T(0), bacc[r] = T(0), sacc[r] = T(0), qacc[r] = 0.0;
+    // One sweep over the tile's elements assembles the load, the diagonal and
+    // the mass coefficients and, in FP64, takes the FP64 corner values of A x
+    // with the same element operator (FP32 tiles take them in the restart
+    // sweep below, which measured faster there): per element 4 values of
+    // width w (7 with the Chebyshev preconditioner's absolute row sums), plus
+    // 3 doubles in FP64, as many elements per chunk as the corner space holds
+    // (chunks split each node's corner sequence without reordering it, so no
+    // sum depends on the chunking).
+    constexpr int eb = (kFusedSetup ? 3 * int(sizeof(double)) : 0) + (CHEB ? 7 : 4) * int(sizeof(T));
+    const int space = 3 * int(sizeof(T)) * (NCH == 1 ? t.n_telem : (t.n_telem + 1) / 2);
+    const int chs = max(1, space / eb);
+    double* qs = reinterpret_cast<double*>(rest);   // [3 chunk] FP64 corner values of A x (FP64 tiles)
+    T* dcs = reinterpret_cast<T*>(qs + (kFusedSetup ? 3 * chs : 0));   // [3 chunk] diagonal corners
+    T* bcs = dcs + 3 * chs;                         // [chunk]   load per corner
+    T* scs = bcs + chs;                             // [3 chunk] absolute row sums per corner (Chebyshev)
     for (int e0 = 0; e0 < t.n_telem; e0 += chs) {
       const int e1 = min(e0 + chs, t.n_telem);
       __syncthreads();
@@ -417,18 +427,28 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
         a.mte[te] = mA;
         const int l = e - e0;
         // diagonal of K^e from the zero row sums
-        dc[3 * l + 0] = kp * -(w01 + w02) + T(2) * mA;
-        dc[3 * l + 1] = kp * -(w01 + w12) + T(2) * mA;
-        dc[3 * l + 2] = kp * -(w02 + w12) + T(2) * mA;
-        bc[3 * chs + l] = qp ? (P.b0 * ph + P.bH * He) * A * T(1.0 / 3.0) : T(0);
+        dcs[3 * l + 0] = kp * -(w01 + w02) + T(2) * mA;
+        dcs[3 * l + 1] = kp * -(w01 + w12) + T(2) * mA;
+        dcs[3 * l + 2] = kp * -(w02 + w12) + T(2) * mA;
+        bcs[l] = qp ? (P.b0 * ph + P.bH * He) * A * T(1.0 / 3.0) : T(0);
         if (CHEB) {
           // off-diagonal entries of the element matrix
           const T o01 = fabs(kp * w01 + mA);
           const T o02 = fabs(kp * w02 + mA);
           const T o12 = fabs(kp * w12 + mA);
-          sc_[3 * l + 0] = dc[3 * l + 0] + o01 + o02;
-          sc_[3 * l + 1] = dc[3 * l + 1] + o01 + o12;
-          sc_[3 * l + 2] = dc[3 * l + 2] + o02 + o12;
+          scs[3 * l + 0] = dcs[3 * l + 0] + o01 + o02;
+          scs[3 * l + 1] = dcs[3 * l + 1] + o01 + o12;
+          scs[3 * l + 2] = dcs[3 * l + 2] + o02 + o12;
+        }
+        if constexpr (kFusedSetup) {
+          const int c0 = a.dm.lc0[te], c1 = a.dm.lc1[te], c2 = a.dm.lc2[te];
+          const double k = double(kp), mm = double(mA);
+          const double d01 = w01, d02 = w02, d12 = w12;
+          const double s0 = sv[c0], s1 = sv[c1], s2 = sv[c2];
+          const double ss = s0 + s1 + s2;
+          qs[3 * l + 0] = k * (d01 * (s1 - s0) + d02 * (s2 - s0)) + mm * (s0 + ss);
+          qs[3 * l + 1] = k * (d01 * (s0 - s1) + d12 * (s2 - s1)) + mm * (s1 + ss);
+          qs[3 * l + 2] = k * (d02 * (s0 - s2) + d12 * (s1 - s2)) + mm * (s2 + ss);
         }
       }
       __syncthreads();
@@ -441,9 +461,10 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
             const int cc = clist[j];
             const int e = cc / 3;
             if (e >= e0 && e < e1) {
-              dacc[r] += dc[cc - 3 * e0];
-              bacc[r] += bc[3 * chs + e - e0];
-              if (CHEB) sacc[r] += sc_[cc - 3 * e0];
+              dacc[r] += dcs[cc - 3 * e0];
+              bacc[r] += bcs[e - e0];
+              if (CHEB) sacc[r] += scs[cc - 3 * e0];
+              if constexpr (kFusedSetup) qacc[r] += qs[cc - 3 * e0];
             }
           }
         }
@@ -455,7 +476,9 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       if (i < t.n_own) {
         const int g = t.node_begin + i;
         if (qp) a.b[g] = bacc[r];
-        a.dinv[g] = T(1) / dacc[r];
+        bset[r] = bacc[r];
+        dset[r] = T(1) / dacc[r];
+        a.dinv[g] = dset[r];
         // Gershgorin bound of D^-1 A, carried to the reduction as -max in the
         // min-combined slot (unused by restart passes)
         if (CHEB) amin = fmin(amin, -double(sacc[r]) / double(dacc[r]));
@@ -468,14 +491,17 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
   double gam = 0.0, del = 0.0, cf = 0.0, ca = -INFINITY, na = 0.0, rb = 0.0;
   if (xpass) {
     // ---- restart / check: true residual b - A x with FP64 corner values ----
-    double qacc[NPT];
-#pragma unroll
-    for (int r = 0; r < NPT; ++r) qacc[r] = 0.0;
+    // (in FP64 the set-up sweep above has already summed them)
     // FP64 corner values: 2 nch chunks in FP32 (3 doubles per element in the
     // space of 6 floats), nch in FP64
     const int nxc = (sizeof(T) == 4 ? 2 : 1) * NCH;
     const int chx = (t.n_telem + nxc - 1) / nxc;
-    for (int e0 = 0; e0 < t.n_telem; e0 += chx) {
+    const bool summed = kFusedSetup && setup;
+    if (!summed) {
+#pragma unroll
+      for (int r = 0; r < NPT; ++r) qacc[r] = 0.0;
+    }
+    for (int e0 = 0; !summed && e0 < t.n_telem; e0 += chx) {
       const int e1 = min(e0 + chx, t.n_telem);
       __syncthreads();
       for (int e = e0 + tid; e < e1; e += kBlock) {
@@ -509,9 +535,10 @@ __global__ __launch_bounds__(kBlock) void k_dmg(DmgArgs<T> a) {
       const int i = tid + r * kBlock;
       if (i >= t.n_own) continue;
       const int g = t.node_begin + i;
-      const T bi = a.b[g];
+      // linear solves read the caller's right-hand side
+      const T bi = (summed && qp) ? bset[r] : a.b[g];
       const T ri = T(double(bi) - qacc[r]);
-      const T di = a.dinv[g];
+      const T di = summed ? dset[r] : a.dinv[g];
       const double sr = double(ri) * double(di);
       T xv = sv[i];
       uint8_t w = HELD_NONE;
