@@ -71,7 +71,7 @@ def test_explicit_element_chunks_agree_bitwise(block):
 
 
 @pytest.mark.parametrize("dtype,tile,precond,monotone", [("f64", 256, 0, 0), ("f32", 512, 0, 0), ("f64", 512, 0, 1),
-                                                         ("f32", 256, 3, 0)])
+                                                         ("f32", 256, 3, 0), ("f64", 256, 3, 0)])
 def test_damage_element_chunks_agree_bitwise(dtype, tile, precond, monotone):
     """One or two element chunks per damage pass add each node's corner values in the same order:
     the same bits in every pass type (set-up, restart / check, first / iterate, Chebyshev)."""
