@@ -143,6 +143,33 @@ def test_fp64_headline_configuration_matches_oracle():
         assert max(errs.values()) < 1e-9, (k, errs)
 
 
+def test_fp64_headline_stepping_modes_agree_bitwise():
+    """The three ways bench.py steps the FP64 headline plate (448-node tiles) give the same states
+    bit for bit: polled steps, windowed steps (convergence read once per window), and steps
+    replayed from HIP graphs (explicit step and the first CG rounds in one graph, continuations
+    as needed), each checked after every window or replay."""
+    from paper_2606_23458_amd import GraphStepper, Simulator
+    p = w.config1().with_(dtype="f64")
+    polled = Simulator(p, dtype="f64", tile_nodes=448)
+    windowed = Simulator(p, dtype="f64", tile_nodes=448, dt=list(polled.dt))
+    graphed = Simulator(p, dtype="f64", tile_nodes=448, dt=list(polled.dt))
+    for sim in (polled, windowed, graphed):
+        sim.step(20)
+    gs = GraphStepper(graphed)   # takes one eager step
+    polled.step()
+    windowed.step()
+    for k in range(3):
+        polled.step(16)
+        windowed.run(16)
+        gs.step(16)
+        torch.cuda.synchronize()
+        for other in (windowed, graphed):
+            assert torch.equal(polled.state.nodes, other.state.nodes), k
+            assert torch.equal(polled.state.H, other.state.H), k
+            assert torch.equal(polled.active, other.active), k
+    assert polled.cg_stats()[0]["flags"] == 0
+
+
 def test_fp64_perforated_configuration_matches_oracle():
     """The perforated plate (AT1, star-convex, plane stress, irregular node valence) in FP64 as
     bench.py times it (448-node tiles): one explicit step from a random state element by element,
