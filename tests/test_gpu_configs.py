@@ -143,16 +143,17 @@ def test_fp64_headline_configuration_matches_oracle():
         assert max(errs.values()) < 1e-9, (k, errs)
 
 
-def test_fp64_headline_stepping_modes_agree_bitwise():
-    """The three ways bench.py steps the FP64 headline plate (448-node tiles) give the same states
-    bit for bit: polled steps, windowed steps (convergence read once per window), and steps
-    replayed from HIP graphs (explicit step and the first CG rounds in one graph, continuations
-    as needed), each checked after every window or replay."""
+@pytest.mark.parametrize("dtype,tile", [("f64", 448), ("f32", 512)])
+def test_headline_stepping_modes_agree_bitwise(dtype, tile):
+    """The three ways bench.py steps the 1024x512 plate (its tile sizes) give the same states bit
+    for bit: polled steps, windowed steps (convergence read once per window), and steps replayed
+    from HIP graphs (explicit step and the first CG rounds in one graph, continuations as
+    needed), each checked after every window or replay."""
     from paper_2606_23458_amd import GraphStepper, Simulator
-    p = w.config1().with_(dtype="f64")
-    polled = Simulator(p, dtype="f64", tile_nodes=448)
-    windowed = Simulator(p, dtype="f64", tile_nodes=448, dt=list(polled.dt))
-    graphed = Simulator(p, dtype="f64", tile_nodes=448, dt=list(polled.dt))
+    p = w.config1().with_(dtype=dtype)
+    polled = Simulator(p, dtype=dtype, tile_nodes=tile)
+    windowed = Simulator(p, dtype=dtype, tile_nodes=tile, dt=list(polled.dt))
+    graphed = Simulator(p, dtype=dtype, tile_nodes=tile, dt=list(polled.dt))
     for sim in (polled, windowed, graphed):
         sim.step(20)
     gs = GraphStepper(graphed)   # takes one eager step
