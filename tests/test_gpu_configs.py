@@ -143,14 +143,15 @@ def test_fp64_headline_configuration_matches_oracle():
         assert max(errs.values()) < 1e-9, (k, errs)
 
 
-@pytest.mark.parametrize("dtype,tile", [("f64", 448), ("f32", 512)])
-def test_headline_stepping_modes_agree_bitwise(dtype, tile):
-    """The three ways bench.py steps the 1024x512 plate (its tile sizes) give the same states bit
-    for bit: polled steps, windowed steps (convergence read once per window), and steps replayed
-    from HIP graphs (explicit step and the first CG rounds in one graph, continuations as
-    needed), each checked after every window or replay."""
+@pytest.mark.parametrize("make,dtype,tile", [(w.config1, "f64", 448), (w.config1, "f32", 512),
+                                             (w.config2, "f32", 512)])
+def test_headline_stepping_modes_agree_bitwise(make, dtype, tile):
+    """The three ways bench.py steps the 1024x512 plate (its tile sizes), and the perforated
+    plate, give the same states bit for bit: polled steps, windowed steps (convergence read once
+    per window), and steps replayed from HIP graphs (explicit step and the first CG rounds in one
+    graph, continuations as needed), each checked after every window or replay."""
     from paper_2606_23458_amd import GraphStepper, Simulator
-    p = w.config1().with_(dtype=dtype)
+    p = make().with_(dtype=dtype)
     polled = Simulator(p, dtype=dtype, tile_nodes=tile)
     windowed = Simulator(p, dtype=dtype, tile_nodes=tile, dt=list(polled.dt))
     graphed = Simulator(p, dtype=dtype, tile_nodes=tile, dt=list(polled.dt))
